@@ -1,0 +1,230 @@
+"""Benchmark: multi-mode difference-map iterations on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1|2]
+
+A step is one full DM iteration (Eq. 3 view update with the modulus
+projection, Eq. 5 object update, Eq. 4 probe update, Eq. 6 errors) over the
+whole synthetic scan, all of it inside libdm's HIP kernels, with every input
+resident in HBM.  Prints one JSON line.  Default workload: 2500 views x 5
+probe modes, 128x128 frames, 1024x1024 object, Poisson 1e5 photons/frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("DM frame·mode/s per iter (plain vs BF16-split/warm-start), "
+          "iters to err≤1e-3")
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1808_10375_amd/csrc/dm_kernels.hpp",
+                  "paper_1808_10375_amd/csrc/dm_fft.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_views_2500x5_128.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_key: str):
+    """HBM bytes per launch of the view kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != launch_key:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def views_alg_bytes(n, m, f):
+    """Algorithmic HBM bytes of one view-update launch: read psi and write
+    psi' (8 F^2 bytes each per view-mode) and read I (4 F^2 per view)."""
+    return n * m * 16 * f * f + n * 4 * f * f
+
+
+def step_alg_bytes(n, m, f):
+    """Algorithmic bytes of a whole iteration: the above plus one more read of
+    psi' by the probe update (24 F^2 + 4 F^2 / M per view-mode)."""
+    return n * m * 24 * f * f + n * 4 * f * f
+
+
+def cpu_baseline(scan, n_sample: int, reps: int = 3):
+    """The FP64 oracle, single-threaded, on the first n_sample views of the
+    same scan (same frame size, modes and object)."""
+    from oracle import dm_oracle as oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    pos = scan.pos[:n_sample]
+    I = scan.I[:n_sample].astype(np.float64)
+    psi = oracle.init_views(scan.P0, scan.O0, pos)
+    P = scan.P0.astype(np.complex128)
+    O = scan.O0.astype(np.complex128)
+    psi, P, O, _ = oracle.iterate(psi, P, O, pos, I, scan.beta)  # warm-up
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        psi, P, O, _ = oracle.iterate(psi, P, O, pos, I, scan.beta)
+        times.append(time.perf_counter() - t0)
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    t = float(np.median(times))
+    m = scan.P0.shape[0]
+    return {"value": n_sample * m / t, "unit": "frame·mode/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"first {n_sample} of {scan.n_frames} views (M={m}, F={scan.frame}, "
+                       f"object {scan.obj_shape[0]}x{scan.obj_shape[1]}), median of {reps} "
+                       f"iterations after 1 warm-up, FP64 numpy, 1 thread; "
+                       f"{t:.2f} s per iteration")}
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(reps: int = 3):
+    """An elementwise kernel that reads COPY_BYTES and writes COPY_BYTES
+    (b = -a in float32), run `reps` times: the reference for the traffic
+    counters."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--conv-iters", type=int, default=100,
+                    help="total iterations from the cold start for the err curve")
+    ap.add_argument("--cpu-sample", type=int, default=300)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--multipass", action="store_true",
+                    help="use the three-kernel transform path instead of the fused one")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the frame-sharded "
+                          "multi-GPU form is a design, not built (use --gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1808_10375_amd import dm, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    if args.config == 1:
+        scan = synth.multimode_spiral_128(1)
+        workload = ("multi-mode spiral: 2500 views x 5 Hermite-Gaussian modes, 128x128 frames, "
+                    "Fermat spiral (10 px step), 1024x1024 object, Poisson 1e5 photons/frame")
+    else:
+        scan = synth.flyscan_raster_256(2)
+        workload = ("fly scan: 10000 views x 8 modes, 256x256 frames, 100x100 raster, "
+                    "3072x3072 object, 8-position motion blur, Poisson 1e6 photons/frame")
+    print(f"# generated {scan.name} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    n, f, m = scan.n_frames, scan.frame, scan.n_modes
+    h, w = scan.obj_shape
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        I = torch.from_numpy(scan.I).to(dev)
+        P0 = torch.from_numpy(scan.P0).to(dev)
+        O0 = torch.from_numpy(scan.O0).to(dev)
+        flags = dm.DM_FLAG_PHASE_TIMING | (dm.DM_FLAG_MULTIPASS if args.multipass else 0)
+        ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream)
+        ctx.iterate(args.warmup)
+        ctx.phase_times()  # drop the warm-up marks (synchronises)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ctx.iterate(args.steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        phases, n_timed = ctx.phase_times()
+        done = args.warmup + args.steps
+        if args.conv_iters > done:
+            ctx.iterate(args.conv_iters - done)
+        hist = ctx.error_history(1, max(args.conv_iters, done))
+        ctx.free()
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n * m / (elapsed / args.steps)
+    views_ms = phases["views"] / max(n_timed, 1)
+    alg = views_alg_bytes(n, m, f)
+    achieved = alg / (views_ms * 1e-3) / 1e9
+    key = f"n{n}_m{m}_f{f}_o{h}x{w}"
+    traffic = measured_traffic(key)
+    errs = [e["eps_probe"] for e in hist]
+    reach = next((i + 1 for i, e in enumerate(errs) if e <= 1e-3), None)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "frame·mode/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n_frames": n, "n_modes": m, "frame": f,
+                   "object": [h, w], "beta": scan.beta,
+                   "precision": "fp32-fft" + ("-multipass" if args.multipass else "")},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": ("k_fourier_fused<%d>" % f) if (f <= 128 and not args.multipass)
+                     else "views (3 kernels)",
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": views_ms},
+        "step_roofline_frac": step_alg_bytes(n, m, f) / (ms_per_step * 1e-3) / 1e9
+        / HBM_PEAK_GBS,
+        "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
+        "iters_to_err_1e-3": reach,
+        "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
+    }
+    if not args.no_cpu:
+        print("# timing the FP64 oracle on a sample of the scan", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scan, min(args.cpu_sample, n))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

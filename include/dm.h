@@ -1,0 +1,200 @@
+/*
+ * dm.h -- C-ABI of libdm: one multi-mode difference-map (DM) ptychography
+ * iteration on an MI355X (gfx950), after Section II of Dong, Fang et al.,
+ * "High-Performance Multi-Mode Ptychography Reconstruction on Distributed
+ * GPUs" (arXiv:1808.10375).
+ *
+ * Problem (Section II, Eqs. 1-2): N views j with integer top-left corners
+ * (y_j, x_j), measured intensities I_j, probe modes P_k (k < M) and one object
+ * O (a single object mode).  The exit wave of view j, mode k is
+ * psi_{j,k} = P_k * O[window_j].  One iteration (dm_iterate) computes:
+ *   1. views   psi <- psi + beta (F^-1 F_c[2 P O - psi] - P O)       (Eq. 3)
+ *              F_c rescales every mode of a view by
+ *              sqrt(I_j / sum_k |F[.]_k|^2) and keeps the phase  (F_c, Eq. 3)
+ *   2. object  O <- sum_j sum_k conj(P_k) psi / sum_j sum_k |P_k|^2  (Eq. 5)
+ *   3. probe   P_k <- sum_j conj(O[win_j]) psi_{j,k}
+ *                     / sum_j |O[win_j]|^2, with the new O            (Eq. 4)
+ *   4. errors  relative L2 change between iterations                  (Eq. 6)
+ * Transform convention: unnormalised forward DFT exp(-2 pi i (ku+lv)/F),
+ * inverse with 1/F^2, detector DC at [0,0] (no fftshift).  Zero mode sums in
+ * F_c give 0; zero denominators in Eqs. 4-5 keep the previous value.
+ *
+ * Layouts (all row-major, complex64 = interleaved {float re, float im}):
+ *   I      float32   [N][F][F]
+ *   pos    int32     [N][2]      (y, x) top-left of each F x F window
+ *   probe  complex64 [M][F][F]
+ *   object complex64 [H][W]
+ *   psi    complex64 [N][M][F][F]
+ *
+ * Memory ownership: every device buffer is the caller's.  I is read in place
+ * and must stay alive and unchanged until dm_free.  probe0/object0 are
+ * copied at dm_init.  All iteration state (psi, P, O, partial sums, error
+ * ring) lives in the caller's workspace of at least dm_workspace_bytes().
+ * The library allocates no device memory; its host-side context is freed by
+ * dm_free.
+ *
+ * Streams: every call enqueues its work on the stream given to dm_init
+ * (a hipStream_t passed as void*; NULL = the default stream).  Only dm_init,
+ * dm_error, dm_error_history and dm_get_state synchronise with that stream.
+ *
+ * Errors: calls return a dm_status and never abort.  After a HIP runtime
+ * error the context is failed for good: every later call returns DM_E_STATE
+ * and dm_last_error() holds the message.  A non-finite error norm (the
+ * iteration diverged) is reported as DM_E_NUMERIC by dm_error.
+ *
+ * Threading: one host thread at a time per context; several contexts may
+ * share a GPU and a stream.
+ */
+#ifndef DM_H_
+#define DM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dm_ctx dm_ctx; /* opaque */
+
+typedef enum {
+  DM_OK = 0,
+  DM_E_ARG = -1,          /* bad descriptor value, null/misaligned pointer,
+                             non-finite intensity                          */
+  DM_E_UNSUPPORTED = -2,  /* valid in the paper but not built: F not a power
+                             of two in [16, 256], M > 16, unknown precision */
+  DM_E_BOUNDS = -3,       /* a window leaves the object                     */
+  DM_E_WORKSPACE = -4,    /* workspace smaller than dm_workspace_bytes()    */
+  DM_E_HIP = -5,          /* HIP runtime error (context becomes failed)     */
+  DM_E_STATE = -6,        /* call on a failed or freed context, or out of
+                             order                                          */
+  DM_E_NUMERIC = -7       /* non-finite error norm: the iteration diverged  */
+} dm_status;
+
+typedef enum {
+  DM_FP32_FFT = 0,        /* FP32 radix FFTs on the vector ALUs             */
+  DM_BF16X3_DFT = 1       /* F = 128 only: each 2-D DFT as two dense GEMMs on
+                             MFMA with BF16 operands split hi + lo (3 terms)
+                             and FP32 accumulation; modulus, norms and the
+                             object normaliser stay FP32/FP64             */
+} dm_precision;
+
+/* dm_desc.flags bits */
+#define DM_FLAG_MULTIPASS 1u     /* use the three-kernel transform path for any
+                                    F (it is always used for F = 256)       */
+#define DM_FLAG_PHASE_TIMING 2u  /* bracket every phase launch of
+                                    dm_iterate with HIP events on the
+                                    context's stream (read by
+                                    dm_phase_times)                          */
+
+/* Phases of one iteration, in launch order (indices of dm_phase_times). */
+#define DM_PHASE_VIEWS 0         /* Eq. 3 with F_c: exit waves, transforms,
+                                    modulus projection, view update         */
+#define DM_PHASE_OBJECT 1        /* Eq. 5: object gather                     */
+#define DM_PHASE_PROBE_PARTIAL 2 /* Eq. 4: per-chunk probe sums              */
+#define DM_PHASE_PROBE_FINAL 3   /* Eq. 4: division, next mode power        */
+#define DM_PHASE_ERRORS 4        /* Eq. 6: error norms into the ring        */
+#define DM_N_PHASES 5
+
+typedef struct {
+  int32_t n_frames;   /* N >= 1                                          */
+  int32_t frame;      /* F: power of two, 16 <= F <= 256                 */
+  int32_t n_modes;    /* M: 1 <= M <= 16 probe modes                     */
+  int32_t obj_h;      /* H >= F                                          */
+  int32_t obj_w;      /* W >= F                                          */
+  float beta;         /* relaxation, 0 <= beta <= 1 (Eq. 3; usually 0.8) */
+  int32_t precision;  /* dm_precision                                    */
+  uint32_t flags;     /* DM_FLAG_* bits, others must be 0                */
+} dm_desc;
+
+#define DM_MAX_MODES 16
+
+typedef struct {
+  int32_t iter;        /* 1-based index of the iteration these belong to  */
+  float eps_psi;       /* ||psi' - psi|| / ||psi'||                       */
+  float eps_obj;       /* ||O' - O|| / ||O'|| over covered object pixels  */
+  float eps_probe;     /* Eq. 6 with the mode sum inside both norms; the
+                          convergence error "err"                        */
+  float eps_probe_mode[DM_MAX_MODES]; /* Eq. 6 per probe mode          */
+} dm_errors;
+
+/* Bytes of device workspace dm_init needs for this problem; 0 if the
+ * descriptor is invalid.  Pure host computation. */
+size_t dm_workspace_bytes(const dm_desc* desc);
+
+/* Validate, build the object-tile -> view lists, copy probe0/object0 into
+ * the workspace and set the initial views psi_j = P0 * O0[window_j]
+ * (Section II: the initial fields are built from the initial guesses).
+ *   out       receives the new context (set to NULL on failure)
+ *   I_dev     device, float32 [N][F][F]; negative values act as 0; any NaN
+ *             or Inf -> DM_E_ARG
+ *   pos_host  host, int32 [N][2] (y, x); 0 <= y <= H-F and 0 <= x <= W-F,
+ *             otherwise DM_E_BOUNDS; copied
+ *   probe0_dev, object0_dev  device complex64, copied
+ *   workspace_dev  device, >= dm_workspace_bytes(desc) bytes, 256-byte
+ *             aligned; owned by the caller, used until dm_free
+ *   hip_stream     hipStream_t or NULL
+ * Synchronises the stream once (to read the intensity check). */
+dm_status dm_init(dm_ctx** out, const dm_desc* desc, const float* I_dev,
+                  const int32_t* pos_host, const void* probe0_dev,
+                  const void* object0_dev, void* workspace_dev,
+                  size_t workspace_bytes, void* hip_stream);
+
+/* Enqueue n_iter >= 0 DM iterations (steps 1-4 above) on the context's
+ * stream.  Asynchronous; the error norms of every iteration go to a device
+ * ring of the last 4096 iterations. */
+dm_status dm_iterate(dm_ctx* ctx, int32_t n_iter);
+
+/* Enqueue a device-to-device copy of the current object, complex64 [H][W]. */
+dm_status dm_get_object(dm_ctx* ctx, void* dst_dev);
+
+/* Enqueue a device-to-device copy of the current probe, complex64 [M][F][F]. */
+dm_status dm_get_probe(dm_ctx* ctx, void* dst_dev);
+
+/* Synchronise and return the error norms of the latest iteration
+ * (iter = 0 and zeros before the first).  DM_E_NUMERIC if any is not
+ * finite. */
+dm_status dm_error(dm_ctx* ctx, dm_errors* out_host);
+
+/* Synchronise and copy the error norms of iterations first..first+count-1
+ * (1-based; each must be among the last 4096 run) to out_host[count]. */
+dm_status dm_error_history(dm_ctx* ctx, int32_t first, int32_t count,
+                           dm_errors* out_host);
+
+/* Number of iterations run so far (host-side count of enqueued ones). */
+int32_t dm_iterations(const dm_ctx* ctx);
+
+/* Copy the full state out (device destinations; any may be NULL to skip):
+ * psi [N][M][F][F], probe [M][F][F], object [H][W]; *iter_host gets the
+ * iteration count.  Synchronises. */
+dm_status dm_get_state(dm_ctx* ctx, void* psi_dst_dev, void* probe_dst_dev,
+                       void* object_dst_dev, int32_t* iter_host);
+
+/* Replace the state (device sources; all three required) and set the
+ * iteration count: exact resume, or a one-step comparison from a given
+ * state.  Asynchronous. */
+dm_status dm_set_state(dm_ctx* ctx, const void* psi_dev, const void* probe_dev,
+                       const void* object_dev, int32_t iter);
+
+/* With DM_FLAG_PHASE_TIMING: synchronise, then write to ms_host[DM_N_PHASES]
+ * the GPU time (milliseconds, from HIP events) spent in each phase by all
+ * iterations enqueued since the previous call, and to *n_iter_host their
+ * number; the accumulators restart.  Without the flag: DM_E_STATE. */
+dm_status dm_phase_times(dm_ctx* ctx, double* ms_host, int32_t* n_iter_host);
+
+/* Release the host-side context.  Does not touch the caller's buffers.
+ * NULL is a no-op. */
+void dm_free(dm_ctx* ctx);
+
+/* Static text for a status code. */
+const char* dm_status_str(dm_status s);
+
+/* Last error message of a context ("" if none); valid until the next call
+ * on it.  With NULL: the last message of a failed dm_init on this thread. */
+const char* dm_last_error(const dm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DM_H_ */

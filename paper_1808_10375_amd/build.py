@@ -1,0 +1,58 @@
+"""Build libdm.so (the gfx950 HIP library behind include/dm.h) in-tree.
+
+    python -m paper_1808_10375_amd.build          # compile
+    python -m paper_1808_10375_amd.build --check  # print resource usage too
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libdm.so")
+
+SOURCES = ["dm_api.hip"]
+HEADERS = ["dm_fft.hpp", "dm_kernels.hpp", os.path.join("..", "..", "include", "dm.h")]
+
+# Packed FP32 instructions are kept out of every kernel.
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found: the HIP library cannot be built")
+
+
+def build(verbose: bool = False, check: bool = False) -> str:
+    """Compile every source into libdm.so (always recompiles)."""
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = LIB + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")]
+    if check:
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
+    cmd += ["-o", tmp] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libdm.so")
+    if check:
+        sys.stdout.write(res.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True, check="--check" in sys.argv)
+    print("built", LIB)

@@ -1,0 +1,829 @@
+// dm_kernels.hpp -- gfx950 kernels of one multi-mode difference-map iteration
+// (Section II of arXiv:1808.10375: Eq. 3 view update with the constrained
+// transform F_c, Eq. 5 object update, Eq. 4 probe update, Eq. 6 errors).
+//
+// Layouts: psi [N][M][F][F], P [M][F][F], O [H][W] (complex64 as float2),
+// I [N][F][F] float, pos [N][2] int (y, x top-left).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <stdint.h>
+
+#include "dm_fft.hpp"
+
+namespace dmk {
+
+// Device copy of the public dm_errors record (same size and field order).
+struct DevErrors {
+  int32_t iter;
+  float eps_psi, eps_obj, eps_probe;
+  float eps_mode[16];
+};
+
+constexpr int kRing = 4096;
+
+// ---------------------------------------------------------------------------
+// block reduction of two floats (fixed order: lanes, then waves in order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum2(float& a, float& b, float* red) {
+  constexpr int NW = (NT + 63) / 64;
+  if constexpr (NT < 64) {
+    // fewer lanes than a wave: plain LDS sum in thread order
+    __shared__ float tmp[2 * 64];
+    __syncthreads();
+    tmp[2 * threadIdx.x] = a;
+    tmp[2 * threadIdx.x + 1] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float sa = 0.f, sb = 0.f;
+      for (int i = 0; i < NT; ++i) { sa += tmp[2 * i]; sb += tmp[2 * i + 1]; }
+      a = sa; b = sb;
+    }
+    return;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float sa = 0.f, sb = 0.f;
+    for (int i = 0; i < NW; ++i) { sa += red[2 * i]; sb += red[2 * i + 1]; }
+    a = sa; b = sb;
+  }
+}
+
+// runtime block size version
+__device__ __forceinline__ void block_sum2_rt(float& a, float& b, float* red) {
+  const int nw = (blockDim.x + 63) >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float sa = 0.f, sb = 0.f;
+    for (int i = 0; i < nw; ++i) { sa += red[2 * i]; sb += red[2 * i + 1]; }
+    a = sa; b = sb;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D transform of one F x F frame held by F*F/16 threads, 16 values each.
+// Thread t = g*F + c.  Spatial layout: a[u1] = x[B*u1 + g][c].
+// Spectral layout:  a[i*B + l2] = X[c][(g + B*i) + 16*l2].
+// buf: LDS, F rows of LD = F + 1 float2 (one padding column).
+// ---------------------------------------------------------------------------
+template <int F, int DIR>
+struct Frame2D {
+  static constexpr int B = F / 16;
+  static constexpr int NI = 16 / B;  // k1 values per thread after the exchange
+  static constexpr int LD = F + 1;
+
+  // forward: spatial -> spectral
+  __device__ __forceinline__ static void fwd(float2 (&a)[16], float2* buf,
+                                             const float2* __restrict__ tw, int c, int g) {
+    static_assert(DIR < 0, "fwd is the forward transform");
+    // columns: 16-point over u1
+    dft16<-1>(a);
+    if constexpr (B > 1) {
+#pragma unroll
+      for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, g * k1, a[k1]);
+      __syncthreads();
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) buf[(k1 * B + g) * LD + c] = a[k1];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) a[i * B + q] = buf[((g + B * i) * B + q) * LD + c];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+    }
+    // transpose to rows: Xc[(g + B i) + 16 k2][c] -> row c of the buffer
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) buf[((g + B * i) + 16 * k2) * LD + c] = a[i * B + k2];
+    __syncthreads();
+#pragma unroll
+    for (int v1 = 0; v1 < 16; ++v1) a[v1] = buf[c * LD + B * v1 + g];
+    // rows: 16-point over v1
+    dft16<-1>(a);
+    if constexpr (B > 1) {
+#pragma unroll
+      for (int l1 = 1; l1 < 16; ++l1) a[l1] = twiddle<-1>(tw, g * l1, a[l1]);
+      __syncthreads();
+#pragma unroll
+      for (int l1 = 0; l1 < 16; ++l1) buf[c * LD + l1 * B + g] = a[l1];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) a[i * B + q] = buf[c * LD + (g + B * i) * B + q];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+    }
+  }
+
+  // inverse (unnormalised): spectral -> spatial, exact mirror of fwd
+  __device__ __forceinline__ static void inv(float2 (&a)[16], float2* buf,
+                                             const float2* __restrict__ tw, int c, int g) {
+    static_assert(DIR > 0, "inv is the inverse transform");
+    if constexpr (B > 1) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) buf[c * LD + (g + B * i) * B + q] = a[i * B + q];
+      __syncthreads();
+#pragma unroll
+      for (int l1 = 0; l1 < 16; ++l1) a[l1] = buf[c * LD + l1 * B + g];
+#pragma unroll
+      for (int l1 = 1; l1 < 16; ++l1) a[l1] = twiddle<1>(tw, g * l1, a[l1]);
+    }
+    dft16<1>(a);
+    __syncthreads();
+#pragma unroll
+    for (int v1 = 0; v1 < 16; ++v1) buf[c * LD + B * v1 + g] = a[v1];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) a[i * B + k2] = buf[((g + B * i) + 16 * k2) * LD + c];
+    if constexpr (B > 1) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) buf[((g + B * i) * B + q) * LD + c] = a[i * B + q];
+      __syncthreads();
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) a[k1] = buf[(k1 * B + g) * LD + c];
+#pragma unroll
+      for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, g * k1, a[k1]);
+    }
+    dft16<1>(a);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Fused view update for F <= 128 (Eq. 3 with F_c): one workgroup per view.
+//   pass 1: for every mode, Z = 2 P O - psi, 2-D DFT, accumulate the mode sum
+//           S = sum_k |Z~_k|^2 in registers (every thread owns the same
+//           spectral pixels for every mode);
+//   scale:  g = sqrt(I / S) / F^2 (0 where S == 0) for the thread's pixels,
+//           parked in a per-view scratch in thread-major order (coalesced,
+//           private to this workgroup, re-read from L2 once per mode);
+//   pass 2: modes in reverse order (the last one's spectrum is still in
+//           registers; the others are recomputed), Z~ * g, inverse DFT -> Z',
+//           psi' = psi + beta (Z' - P O), with psi held in registers (F < 128)
+//           or read once more (F = 128, whose register budget is spent).  The object numerator of
+//           the view, sum_k conj(P_k) psi'_k, accumulates in registers and is
+//           written once; so are the two partial sums of eps_psi.
+// Workgroup b takes view order[slot(b)]: consecutive workgroups go to
+// different XCDs, so each XCD walks its own spatially compact run of views
+// and keeps its part of the object in its L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_slot(int b, int nblocks) {
+  // b -> (b % 8) * ceil(n / 8) + b / 8, clamped for the ragged last group
+  const int per = (nblocks + 7) >> 3;
+  const int x = b & 7, k = b >> 3;
+  const int full = nblocks - (per - 1) * 8;  // XCD groups that get `per` items
+  return (x < full) ? x * per + k : full * per + (x - full) * (per - 1) + k;
+}
+
+template <int F>
+__global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
+    float2* __restrict__ psi, const float* __restrict__ I, const float2* __restrict__ P,
+    const float2* __restrict__ O, const int* __restrict__ pos, const int* __restrict__ order,
+    const float2* __restrict__ tw, float2* __restrict__ opart, float* __restrict__ gscr,
+    float* __restrict__ err_psi, int N, int M, int H, int W, float beta) {
+  constexpr int B = F / 16;
+  constexpr int NT = F * B;
+  constexpr int LD = F + 1;
+  constexpr int FF = F * F;
+  __shared__ float2 buf[F * LD];
+  __shared__ float red[2 * ((NT + 63) / 64)];
+
+  const int t = threadIdx.x;
+  const int j = order[xcd_slot(blockIdx.x, N)];
+  const int c = t % F;
+  const int g = wave_uniform_div<F>(t);
+  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  // buffers: this view's modes, the probe, the object, this view's scale
+  const rsrc_t rpsi = make_rsrc(psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
+  const rsrc_t rP = make_rsrc(P, (uint32_t)(M * FF * 8));
+  const rsrc_t rO = make_rsrc(O, (uint32_t)((size_t)H * W * 8));
+  const rsrc_t rg = make_rsrc(gscr + (size_t)j * FF, (uint32_t)(FF * 4));
+  // per-lane byte offsets (row g of each block of B rows, column c)
+  const int vF = (g * F + c) * 8;
+  const int vO = (g * W + c) * 8;
+  const int sO = (y0 * W + x0) * 8;
+  const int vG = t * 4;
+
+  // F = 128 runs 1024 threads with at most 128 VGPRs each: the view is read
+  // again in the epilogue instead of being held through both transforms.
+  constexpr bool kHold = (F < 128);
+  float2 a[16];
+  float2 hold[kHold ? 16 : 1];
+  {
+    float S[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[r] = 0.f;
+
+    // ---- pass 1: mode sum of |DFT(2 phi - psi)|^2
+    for (int m = 0; m < M; ++m) {
+      const int sm = m * FF * 8;
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) {
+        const int srow = u1 * B * F * 8;
+        const float2 ps = bload2(rpsi, vF, sm + srow);
+        const float2 phi = cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
+        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+        if constexpr (kHold) hold[u1] = ps;
+        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      Frame2D<F, -1>::fwd(a, buf, tw, c, g);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S[r] += cabs2(a[r]);
+    }
+
+    // ---- modulus scale: stage I through LDS (padded rows), form g, park it
+    float* bI = reinterpret_cast<float*>(buf);
+    const float* __restrict__ Ij = I + (size_t)j * FF;
+    __syncthreads();
+    for (int e = t; e < FF; e += NT) bI[(e / F) * (F + 1) + (e % F)] = Ij[e];
+    __syncthreads();
+    const float inv_ff = 1.0f / (float)FF;
+#pragma unroll
+    for (int i = 0; i < 16 / B; ++i)
+#pragma unroll
+      for (int l2 = 0; l2 < B; ++l2) {
+        const int r = i * B + l2;
+        const int l = (g + B * i) + 16 * l2;
+        const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
+        const float sv = S[r];
+        S[r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+      }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[r]), rg, vG, r * NT * 4, 0);
+  }
+
+  // ---- pass 2: projected spectra back to views, modes in reverse order
+  float2 oacc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
+  float e_d = 0.f, e_n = 0.f;
+
+  for (int m = M - 1; m >= 0; --m) {
+    const int sm = m * FF * 8;
+    if (m != M - 1) {
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) {
+        const int srow = u1 * B * F * 8;
+        const float2 ps = bload2(rpsi, vF, sm + srow);
+        const float2 phi =
+            cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
+        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+        if constexpr (kHold) hold[u1] = ps;
+        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      Frame2D<F, -1>::fwd(a, buf, tw, c, g);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], bload1(rg, vG, r * NT * 4));
+    Frame2D<F, 1>::inv(a, buf, tw, c, g);
+#pragma unroll
+    for (int u1 = 0; u1 < 16; ++u1) {
+      const int srow = u1 * B * F * 8;
+      const float2 pr = bload2(rP, vF, sm + srow);
+      const float2 phi = cmul(pr, bload2(rO, vO, sO + u1 * B * W * 8));
+      const float2 ps = kHold ? hold[kHold ? u1 : 0] : bload2(rpsi, vF, sm + srow);
+      const float2 d = make_float2(beta * (a[u1].x - phi.x), beta * (a[u1].y - phi.y));
+      const float2 pn = cadd(ps, d);
+      bstore2(rpsi, pn, vF, sm + srow);
+      e_d += cabs2(d);
+      e_n += cabs2(pn);
+      oacc[u1] = cadd(oacc[u1], cmulc(pr, pn));
+      if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  const rsrc_t ropart = make_rsrc(opart + (size_t)j * FF, (uint32_t)(FF * 8));
+#pragma unroll
+  for (int u1 = 0; u1 < 16; ++u1) bstore2(ropart, oacc[u1], vF, u1 * B * F * 8);
+
+  block_sum2<NT>(e_d, e_n, red);
+  if (t == 0) {
+    err_psi[2 * j] = e_d;
+    err_psi[2 * j + 1] = e_n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-pass view update (any F = 16 B, used for F = 256): three kernels
+// around a spectrum buffer T [N][M][F][F].
+// ---------------------------------------------------------------------------
+// rows per block of the row kernels: up to 256 threads, B threads per row
+template <int F>
+struct RowCfg {
+  static constexpr int B = F / 16;
+  static constexpr int RB = (256 / B < F) ? 256 / B : F;
+  static constexpr int NT = RB * B;
+};
+
+// (1) Z = 2 P O - psi and the DFT along rows, RB rows per block.
+template <int F>
+__global__ __launch_bounds__(256) void k_rows_fwd(
+    const float2* __restrict__ psi, const float2* __restrict__ P, const float2* __restrict__ O,
+    const int* __restrict__ pos, const float2* __restrict__ tw, float2* __restrict__ T,
+    int M, int W) {
+  constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
+  __shared__ float2 buf[RB * LD];
+  const int t = threadIdx.x;
+  const int jm = blockIdx.x;
+  const int j = jm / M, m = jm % M;
+  const int rl = t / B, n2 = t % B;
+  const int row = blockIdx.y * RB + rl;
+  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const float2* __restrict__ pm = psi + (size_t)jm * FF + (size_t)row * F;
+  const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
+  const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
+  float2 a[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int v = B * n1 + n2;
+    const float2 phi = cmul(Pm[v], Or[v]);
+    const float2 ps = pm[v];
+    a[n1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+  }
+  dft16<-1>(a);
+  if constexpr (B > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, n2 * k1, a[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) buf[rl * LD + k1 * B + n2] = a[k1];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int q = 0; q < B; ++q) a[i * B + q] = buf[rl * LD + (n2 + B * i) * B + q];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+  }
+  float2* __restrict__ Tr = T + (size_t)jm * FF + (size_t)row * F;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) Tr[(n2 + B * i) + 16 * k2] = a[i * B + k2];
+}
+
+// (2) DFT along columns for CB columns of every mode of one view, the mode
+// sum, the modulus scale, and the inverse DFT along columns, in place in T.
+// Block = CB * B * M threads; dynamic LDS = CB * M * (F + 1) float2.
+template <int F>
+__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ T, const float* __restrict__ I,
+                                               const float2* __restrict__ tw, int M, int CB) {
+  constexpr int B = F / 16, LD = F + 1, FF = F * F, NI = 16 / B;
+  extern __shared__ float2 dyn[];
+  const int t = threadIdx.x;
+  const int j = blockIdx.x;
+  const int col0 = blockIdx.y * CB;
+  const int c = t % CB;
+  const int rest = t / CB;
+  const int n2 = rest % B;
+  const int m = rest / B;
+  const int line = m * CB + c;
+  float2* __restrict__ Tm = T + ((size_t)j * M + m) * FF + col0 + c;
+  float2 a[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) a[n1] = Tm[(size_t)(B * n1 + n2) * F];
+  dft16<-1>(a);
+  if constexpr (B > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, n2 * k1, a[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) dyn[line * LD + k1 * B + n2] = a[k1];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int q = 0; q < B; ++q) a[i * B + q] = dyn[line * LD + (n2 + B * i) * B + q];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+  }
+  // mode sum through LDS (aliases the exchange buffer)
+  float* s = reinterpret_cast<float*>(dyn);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) s[line * F + (n2 + B * i) + 16 * k2] = cabs2(a[i * B + k2]);
+  __syncthreads();
+  const float* __restrict__ Ij = I + (size_t)j * FF + col0 + c;
+  const float inv_ff = 1.0f / (float)FF;
+  float gs[16];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const int kk = (n2 + B * i) + 16 * k2;
+      float sum = 0.f;
+      for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + c) * F + kk];
+      const float iv = fmaxf(Ij[(size_t)kk * F], 0.f);
+      gs[i * B + k2] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], gs[r]);
+  __syncthreads();
+  if constexpr (B > 1) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int q = 0; q < B; ++q) dyn[line * LD + (n2 + B * i) * B + q] = a[i * B + q];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) a[k1] = dyn[line * LD + k1 * B + n2];
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, n2 * k1, a[k1]);
+  }
+  dft16<1>(a);
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) Tm[(size_t)(B * n1 + n2) * F] = a[n1];
+}
+
+// (3) inverse DFT along rows, psi' = psi + beta (Z' - P O), object numerator
+// of the view and eps_psi partial sums; all modes of RB rows per block.
+template <int F>
+__global__ __launch_bounds__(256) void k_rows_inv(
+    float2* __restrict__ psi, const float2* __restrict__ P, const float2* __restrict__ O,
+    const int* __restrict__ pos, const float2* __restrict__ tw, const float2* __restrict__ T,
+    float2* __restrict__ opart, float* __restrict__ err_psi, int M, int W, float beta) {
+  constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
+  constexpr int NT = RowCfg<F>::NT;
+  __shared__ float2 buf[RB * LD];
+  __shared__ float red[2 * ((NT + 63) / 64)];
+  const int t = threadIdx.x;
+  const int j = blockIdx.x;
+  const int rl = t / B, n2 = t % B;
+  const int row = blockIdx.y * RB + rl;
+  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
+  float2 oacc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
+  float e_d = 0.f, e_n = 0.f;
+  for (int m = 0; m < M; ++m) {
+    const size_t base = ((size_t)j * M + m) * FF + (size_t)row * F;
+    const float2* __restrict__ Tr = T + base;
+    float2 a[16];
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) a[i * B + k2] = Tr[(n2 + B * i) + 16 * k2];
+    if constexpr (B > 1) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int q = 0; q < B; ++q) buf[rl * LD + (n2 + B * i) * B + q] = a[i * B + q];
+      __syncthreads();
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) a[k1] = buf[rl * LD + k1 * B + n2];
+#pragma unroll
+      for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, n2 * k1, a[k1]);
+    }
+    dft16<1>(a);
+    float2* __restrict__ pm = psi + base;
+    const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+      const int v = B * n1 + n2;
+      const float2 pr = Pm[v];
+      const float2 phi = cmul(pr, Or[v]);
+      const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
+      const float2 pn = cadd(pm[v], d);
+      pm[v] = pn;
+      e_d += cabs2(d);
+      e_n += cabs2(pn);
+      oacc[n1] = cadd(oacc[n1], cmulc(pr, pn));
+    }
+  }
+  float2* __restrict__ oj = opart + (size_t)j * FF + (size_t)row * F;
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) oj[B * n1 + n2] = oacc[n1];
+  block_sum2<NT>(e_d, e_n, red);
+  if (t == 0) {
+    const int part = j * gridDim.y + blockIdx.y;
+    err_psi[2 * part] = e_d;
+    err_psi[2 * part + 1] = e_n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Object update (Eq. 5) as an atomics-free gather: one block of 256 threads
+// per T x T object tile walks the list of views whose window meets the tile,
+// in ascending view order, and sums their per-view numerators
+// sum_k conj(P_k) psi'_k and the mode power D = sum_k |P_k|^2.  Views are
+// taken four at a time so their loads are in flight together; each pixel
+// still adds them in ascending order.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_object(
+    const float2* __restrict__ opart, const float* __restrict__ D, float2* __restrict__ O,
+    const int* __restrict__ pos, const int* __restrict__ tile_ptr,
+    const int* __restrict__ tile_views, int F, int H, int W, int tiles_x,
+    float* __restrict__ err_obj) {
+  constexpr int PPT = T * T / 256;  // pixels per thread
+  constexpr int RSTEP = 256 / T;    // rows between a thread's pixels
+  __shared__ float red[8];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int ty = tile / tiles_x, tx = tile % tiles_x;
+  const int col = t % T, row0 = t / T;
+  const int cx = tx * T + col;
+  const int ry = ty * T + row0;
+  float2 num[PPT];
+  float den[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) { num[q] = make_float2(0.f, 0.f); den[q] = 0.f; }
+  const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
+  const size_t FF = (size_t)F * F;
+  constexpr int U = 4;
+  int e = e0;
+  for (; e + U <= e1; e += U) {
+    float2 vv[U][PPT];
+    float dd[U][PPT];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int jv = tile_views[e + k];
+      const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
+      const int v = cx - xj;
+      const float2* __restrict__ oj = opart + (size_t)jv * FF;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int u = ry + RSTEP * q - yj;
+        const bool in = ((unsigned)v < (unsigned)F) && ((unsigned)u < (unsigned)F);
+        vv[k][q] = in ? oj[(size_t)u * F + v] : make_float2(0.f, 0.f);
+        dd[k][q] = in ? D[u * F + v] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) { num[q] = cadd(num[q], vv[k][q]); den[q] += dd[k][q]; }
+  }
+  for (; e < e1; ++e) {
+    const int jv = tile_views[e];
+    const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
+    const int v = cx - xj;
+    const float2* __restrict__ oj = opart + (size_t)jv * FF;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int u = ry + RSTEP * q - yj;
+      if (((unsigned)v < (unsigned)F) && ((unsigned)u < (unsigned)F)) {
+        num[q] = cadd(num[q], oj[(size_t)u * F + v]);
+        den[q] += D[u * F + v];
+      }
+    }
+  }
+  float e_d = 0.f, e_n = 0.f;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int r = ry + RSTEP * q;
+    if (r < H && cx < W && den[q] > 0.f) {
+      const float inv = 1.0f / den[q];
+      const float2 on = make_float2(num[q].x * inv, num[q].y * inv);
+      const float2 oo = O[(size_t)r * W + cx];
+      e_d += cabs2(csub(on, oo));
+      e_n += cabs2(on);
+      O[(size_t)r * W + cx] = on;
+    }
+  }
+  block_sum2<256>(e_d, e_n, red);
+  if (t == 0) {
+    err_obj[2 * tile] = e_d;
+    err_obj[2 * tile + 1] = e_n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe update (Eq. 4), stage 1: per chunk of views (consecutive in the
+// spatial view order) and block of 256 probe pixels,
+// sum_j conj(O'[win_j]) psi'_{j,k} for every mode and sum_j |O'[win_j]|^2.
+// Modes in groups of 8 held in registers; two views' loads in flight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_probe_partial(
+    const float2* __restrict__ psi, const float2* __restrict__ O, const int* __restrict__ pos,
+    const int* __restrict__ order, int N, int M, int F, int W, int chunk,
+    float2* __restrict__ num_part, float* __restrict__ den_part) {
+  const int FF = F * F;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  const int cidx = blockIdx.y;
+  const int j0 = cidx * chunk;
+  const int j1 = min(N, j0 + chunk);
+  const int u = pix / F, v = pix % F;
+  for (int mg = 0; mg < M; mg += 8) {
+    float2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = make_float2(0.f, 0.f);
+    float den = 0.f;
+    int i = j0;
+    for (; i + 2 <= j1; i += 2) {
+      float2 o[2], w[2][8];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int jv = order[i + k];
+        const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
+        o[k] = O[(size_t)(yj + u) * W + xj + v];
+        const float2* __restrict__ pj = psi + ((size_t)jv * M + mg) * FF + pix;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          w[k][q] = (mg + q < M) ? pj[(size_t)q * FF] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        den += cabs2(o[k]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmulc(o[k], w[k][q]));
+      }
+    }
+    for (; i < j1; ++i) {
+      const int jv = order[i];
+      const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
+      const float2 o = O[(size_t)(yj + u) * W + xj + v];
+      den += cabs2(o);
+      const float2* __restrict__ pj = psi + ((size_t)jv * M + mg) * FF + pix;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (mg + q < M) acc[q] = cadd(acc[q], cmulc(o, pj[(size_t)q * FF]));
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (mg + q < M) num_part[((size_t)cidx * M + mg + q) * FF + pix] = acc[q];
+    if (mg == 0) den_part[(size_t)cidx * FF + pix] = den;
+  }
+}
+
+// Probe update, stage 2: fixed-order sum over chunks, division (zero
+// denominators keep the old value), per-mode eps_P partials and the mode
+// power D = sum_k |P'_k|^2 used by the next object update.
+__global__ __launch_bounds__(256) void k_probe_final(
+    const float2* __restrict__ num_part, const float* __restrict__ den_part,
+    float2* __restrict__ P, float* __restrict__ D, int C, int M, int FF,
+    float* __restrict__ err_probe) {
+  __shared__ float red[8];
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  float den = 0.f;
+  for (int cc = 0; cc < C; ++cc) den += den_part[(size_t)cc * FF + pix];
+  float dsum = 0.f;
+  for (int m = 0; m < M; ++m) {
+    float2 num = make_float2(0.f, 0.f);
+    for (int cc = 0; cc < C; ++cc) num = cadd(num, num_part[((size_t)cc * M + m) * FF + pix]);
+    const float2 po = P[(size_t)m * FF + pix];
+    float2 pn = po;
+    if (den > 0.f) {
+      const float inv = 1.0f / den;
+      pn = make_float2(num.x * inv, num.y * inv);
+    }
+    P[(size_t)m * FF + pix] = pn;
+    float e_d = cabs2(csub(pn, po)), e_n = cabs2(pn);
+    dsum += e_n;
+    block_sum2<256>(e_d, e_n, red);
+    if (threadIdx.x == 0) {
+      err_probe[((size_t)blockIdx.x * M + m) * 2] = e_d;
+      err_probe[((size_t)blockIdx.x * M + m) * 2 + 1] = e_n;
+    }
+  }
+  D[pix] = dsum;
+}
+
+// ---------------------------------------------------------------------------
+// Error norms (Eq. 6): fixed-order FP64 sums of the partials, written to the
+// ring slot of this iteration; the device iteration counter advances.
+// ---------------------------------------------------------------------------
+__device__ double block_sum_d(double x, double* red) {
+  const int t = threadIdx.x;
+  red[t] = x;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_errors(
+    const float* __restrict__ err_psi, int n_psi, const float* __restrict__ err_obj, int n_obj,
+    const float* __restrict__ err_probe, int n_pblk, int M, int* __restrict__ counter,
+    DevErrors* __restrict__ ring, int* __restrict__ flags) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double v[4];
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int i = t; i < n_psi; i += 256) { s0 += err_psi[2 * i]; s1 += err_psi[2 * i + 1]; }
+  for (int i = t; i < n_obj; i += 256) { s2 += err_obj[2 * i]; s3 += err_obj[2 * i + 1]; }
+  v[0] = block_sum_d(s0, red);
+  v[1] = block_sum_d(s1, red);
+  v[2] = block_sum_d(s2, red);
+  v[3] = block_sum_d(s3, red);
+  double pd_tot = 0, pn_tot = 0;
+  float modes[16];
+  for (int m = 0; m < M; ++m) {
+    double a = 0, b = 0;
+    for (int i = t; i < n_pblk; i += 256) {
+      a += err_probe[((size_t)i * M + m) * 2];
+      b += err_probe[((size_t)i * M + m) * 2 + 1];
+    }
+    a = block_sum_d(a, red);
+    b = block_sum_d(b, red);
+    pd_tot += a;
+    pn_tot += b;
+    modes[m] = (b > 0) ? (float)sqrt(a / b) : (a > 0 ? INFINITY : 0.f);
+  }
+  if (t == 0) {
+    const int it = *counter;
+    DevErrors e;
+    e.iter = it + 1;
+    e.eps_psi = (v[1] > 0) ? (float)sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.f);
+    e.eps_obj = (v[3] > 0) ? (float)sqrt(v[2] / v[3]) : (v[2] > 0 ? INFINITY : 0.f);
+    e.eps_probe = (pn_tot > 0) ? (float)sqrt(pd_tot / pn_tot) : (pd_tot > 0 ? INFINITY : 0.f);
+    bool bad = !isfinite(e.eps_psi) || !isfinite(e.eps_obj) || !isfinite(e.eps_probe);
+    for (int m = 0; m < 16; ++m) {
+      e.eps_mode[m] = (m < M) ? modes[m] : 0.f;
+      if (m < M && !isfinite(modes[m])) bad = true;
+    }
+    ring[it % kRing] = e;
+    *counter = it + 1;
+    if (bad) *flags |= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+// ---------------------------------------------------------------------------
+// psi_{j,k} = P_k * O[window_j]; one block per (view, mode)
+__global__ __launch_bounds__(256) void k_init_psi(float2* __restrict__ psi,
+                                                  const float2* __restrict__ P,
+                                                  const float2* __restrict__ O,
+                                                  const int* __restrict__ pos, int M, int F,
+                                                  int W) {
+  const int jm = blockIdx.x;
+  const int j = jm / M, m = jm % M;
+  const int FF = F * F;
+  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  for (int p = threadIdx.x; p < FF; p += blockDim.x) {
+    const int u = p / F, v = p % F;
+    psi[(size_t)jm * FF + p] = cmul(P[(size_t)m * FF + p], O[(size_t)(y0 + u) * W + x0 + v]);
+  }
+}
+
+// D = sum_k |P_k|^2
+__global__ __launch_bounds__(256) void k_mode_power(const float2* __restrict__ P,
+                                                    float* __restrict__ D, int M, int FF) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= FF) return;
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) s += cabs2(P[(size_t)m * FF + p]);
+  D[p] = s;
+}
+
+// flags |= 2 if any intensity is NaN or Inf
+__global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ I, size_t n,
+                                                      int* __restrict__ flags) {
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(I[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, 2);
+}
+
+// small fills (used instead of memset so the sequence stays graph-safe)
+__global__ void k_fill_int(int* __restrict__ p, int n, int val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+}  // namespace dmk

@@ -1,0 +1,304 @@
+"""Thin ctypes binding of libdm (include/dm.h) over torch device buffers.
+
+Every function keeps the C name and only marshals arguments: torch tensors
+become device pointers, the current torch stream becomes the hipStream_t.
+All arithmetic runs in libdm's HIP kernels; when the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdm.so")
+
+DM_OK = 0
+DM_E_ARG = -1
+DM_E_UNSUPPORTED = -2
+DM_E_BOUNDS = -3
+DM_E_WORKSPACE = -4
+DM_E_HIP = -5
+DM_E_STATE = -6
+DM_E_NUMERIC = -7
+
+DM_FP32_FFT = 0
+DM_BF16X3_DFT = 1
+DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 256)
+DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
+DM_MAX_MODES = 16
+PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]
+
+EXPORTED = [
+    "dm_workspace_bytes", "dm_init", "dm_iterate", "dm_get_object", "dm_get_probe",
+    "dm_error", "dm_error_history", "dm_iterations", "dm_get_state", "dm_set_state",
+    "dm_free", "dm_status_str", "dm_last_error", "dm_phase_times",
+]
+
+
+class dm_desc(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("frame", ctypes.c_int32),
+                ("n_modes", ctypes.c_int32), ("obj_h", ctypes.c_int32),
+                ("obj_w", ctypes.c_int32), ("beta", ctypes.c_float),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class dm_errors(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("eps_psi", ctypes.c_float),
+                ("eps_obj", ctypes.c_float), ("eps_probe", ctypes.c_float),
+                ("eps_probe_mode", ctypes.c_float * DM_MAX_MODES)]
+
+    def to_dict(self, n_modes: int) -> dict:
+        return {"iter": self.iter, "eps_psi": self.eps_psi, "eps_obj": self.eps_obj,
+                "eps_probe": self.eps_probe,
+                "eps_probe_mode": [self.eps_probe_mode[k] for k in range(n_modes)]}
+
+
+class DMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1808_10375_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    L.dm_workspace_bytes.argtypes = [ctypes.POINTER(dm_desc)]
+    L.dm_workspace_bytes.restype = u64
+    L.dm_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(dm_desc), vp,
+                          ctypes.POINTER(i32), vp, vp, vp, u64, vp]
+    L.dm_init.restype = i32
+    L.dm_iterate.argtypes = [vp, i32]
+    L.dm_iterate.restype = i32
+    L.dm_get_object.argtypes = [vp, vp]
+    L.dm_get_object.restype = i32
+    L.dm_get_probe.argtypes = [vp, vp]
+    L.dm_get_probe.restype = i32
+    L.dm_error.argtypes = [vp, ctypes.POINTER(dm_errors)]
+    L.dm_error.restype = i32
+    L.dm_error_history.argtypes = [vp, i32, i32, ctypes.POINTER(dm_errors)]
+    L.dm_error_history.restype = i32
+    L.dm_iterations.argtypes = [vp]
+    L.dm_iterations.restype = i32
+    L.dm_get_state.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32)]
+    L.dm_get_state.restype = i32
+    L.dm_set_state.argtypes = [vp, vp, vp, vp, i32]
+    L.dm_set_state.restype = i32
+    L.dm_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    L.dm_phase_times.restype = i32
+    L.dm_free.argtypes = [vp]
+    L.dm_free.restype = None
+    L.dm_status_str.argtypes = [i32]
+    L.dm_status_str.restype = ctypes.c_char_p
+    L.dm_last_error.argtypes = [vp]
+    L.dm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def make_desc(n_frames, frame, n_modes, obj_h, obj_w, beta=0.8, precision=DM_FP32_FFT,
+              flags=0) -> dm_desc:
+    return dm_desc(int(n_frames), int(frame), int(n_modes), int(obj_h), int(obj_w),
+                   float(beta), int(precision), int(flags))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    h = getattr(stream, "cuda_stream", stream)
+    return int(h) if h else None
+
+
+def dm_status_str(status: int) -> str:
+    return lib().dm_status_str(int(status)).decode()
+
+
+def dm_last_error(ctx=None) -> str:
+    return lib().dm_last_error(ctx).decode()
+
+
+def _check(status: int, ctx=None):
+    if status != DM_OK:
+        raise DMError(status, f"{dm_status_str(status)}: {dm_last_error(ctx)}")
+
+
+def dm_workspace_bytes(desc: dm_desc) -> int:
+    return int(lib().dm_workspace_bytes(ctypes.byref(desc)))
+
+
+def dm_init(desc: dm_desc, I, pos, probe0, object0, workspace, stream=None):
+    """Returns the opaque context handle.  I, probe0, object0 and workspace are
+    torch device tensors; pos is a host int32 array [N][2]."""
+    pos = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
+    if pos.shape != (desc.n_frames, 2):
+        raise ValueError(f"pos must have shape ({desc.n_frames}, 2)")
+    ctx = ctypes.c_void_p()
+    st = lib().dm_init(ctypes.byref(ctx), ctypes.byref(desc), _ptr(I),
+                       pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(probe0),
+                       _ptr(object0), _ptr(workspace), int(workspace.numel()
+                                                            * workspace.element_size()),
+                       _stream_handle(stream))
+    _check(st, None)
+    return ctx
+
+
+def dm_iterate(ctx, n_iter: int):
+    _check(lib().dm_iterate(ctx, int(n_iter)), ctx)
+
+
+def dm_get_object(ctx, dst):
+    _check(lib().dm_get_object(ctx, _ptr(dst)), ctx)
+
+
+def dm_get_probe(ctx, dst):
+    _check(lib().dm_get_probe(ctx, _ptr(dst)), ctx)
+
+
+def dm_error(ctx) -> dm_errors:
+    out = dm_errors()
+    _check(lib().dm_error(ctx, ctypes.byref(out)), ctx)
+    return out
+
+
+def dm_error_history(ctx, first: int, count: int):
+    arr = (dm_errors * max(count, 1))()
+    _check(lib().dm_error_history(ctx, int(first), int(count), arr), ctx)
+    return [arr[i] for i in range(count)]
+
+
+def dm_iterations(ctx) -> int:
+    return int(lib().dm_iterations(ctx))
+
+
+def dm_get_state(ctx, psi_dst=None, probe_dst=None, object_dst=None) -> int:
+    it = ctypes.c_int32()
+    _check(lib().dm_get_state(ctx, _ptr(psi_dst), _ptr(probe_dst), _ptr(object_dst),
+                              ctypes.byref(it)), ctx)
+    return int(it.value)
+
+
+def dm_set_state(ctx, psi, probe, obj, iteration: int = 0):
+    _check(lib().dm_set_state(ctx, _ptr(psi), _ptr(probe), _ptr(obj), int(iteration)), ctx)
+
+
+def dm_phase_times(ctx):
+    """(dict phase -> milliseconds, iterations) since the previous call."""
+    arr = (ctypes.c_double * len(PHASES))()
+    n = ctypes.c_int32()
+    _check(lib().dm_phase_times(ctx, arr, ctypes.byref(n)), ctx)
+    return {p: arr[i] for i, p in enumerate(PHASES)}, int(n.value)
+
+
+def dm_free(ctx):
+    if ctx:
+        lib().dm_free(ctx)
+
+
+class DMContext:
+    """Owns the torch buffers of one reconstruction and its context handle."""
+
+    def __init__(self, I, pos, probe0, object0, beta=0.8, precision=DM_FP32_FFT, flags=0,
+                 stream=None):
+        import torch
+        if I.dtype != torch.float32 or not I.is_cuda:
+            raise TypeError("I must be a float32 CUDA tensor [N][F][F]")
+        n, f, f2 = I.shape
+        m = probe0.shape[0]
+        h, w = object0.shape
+        self.desc = make_desc(n, f, m, h, w, beta, precision, flags)
+        nbytes = dm_workspace_bytes(self.desc)
+        if nbytes == 0:
+            raise DMError(DM_E_ARG, "invalid problem description")
+        self.device = I.device
+        self.I = I.contiguous()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._p0 = probe0.to(self.device, torch.complex64).contiguous()
+        self._o0 = object0.to(self.device, torch.complex64).contiguous()
+        self.pos = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
+        self.stream = stream
+        self.ctx = dm_init(self.desc, self.I, self.pos, self._p0, self._o0, self.workspace,
+                           stream)
+
+    @property
+    def n_modes(self):
+        return self.desc.n_modes
+
+    def iterate(self, n: int = 1):
+        dm_iterate(self.ctx, n)
+
+    def object(self):
+        import torch
+        out = torch.empty((self.desc.obj_h, self.desc.obj_w), dtype=torch.complex64,
+                          device=self.device)
+        dm_get_object(self.ctx, out)
+        return out
+
+    def probe(self):
+        import torch
+        f = self.desc.frame
+        out = torch.empty((self.desc.n_modes, f, f), dtype=torch.complex64, device=self.device)
+        dm_get_probe(self.ctx, out)
+        return out
+
+    def errors(self) -> dict:
+        return dm_error(self.ctx).to_dict(self.n_modes)
+
+    def error_history(self, first: int = 1, count: Optional[int] = None):
+        if count is None:
+            count = dm_iterations(self.ctx) - first + 1
+        return [e.to_dict(self.n_modes) for e in dm_error_history(self.ctx, first, count)]
+
+    def state(self):
+        import torch
+        d = self.desc
+        psi = torch.empty((d.n_frames, d.n_modes, d.frame, d.frame), dtype=torch.complex64,
+                          device=self.device)
+        P = torch.empty((d.n_modes, d.frame, d.frame), dtype=torch.complex64, device=self.device)
+        O = torch.empty((d.obj_h, d.obj_w), dtype=torch.complex64, device=self.device)
+        it = dm_get_state(self.ctx, psi, P, O)
+        return psi, P, O, it
+
+    def set_state(self, psi, P, O, iteration: int = 0):
+        import torch
+        self._state_keep = [t.to(self.device, torch.complex64).contiguous() for t in (psi, P, O)]
+        dm_set_state(self.ctx, *self._state_keep, iteration)
+
+    def phase_times(self):
+        return dm_phase_times(self.ctx)
+
+    @property
+    def iterations(self) -> int:
+        return dm_iterations(self.ctx)
+
+    def free(self):
+        if getattr(self, "ctx", None):
+            dm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -13,15 +13,15 @@ numpy's unnormalised forward FFT with exp(-2*pi*i*k*n/F), detector DC at [0,0]
 (no fftshift); the reconstruction must use the same convention.
 
 Workload shapes follow the paper's cases as restated for this project:
-  config 0  single mode, 32x32 frames, 10x10 jittered raster, 128x128 object,
+  single_mode_raster_32   single mode, 32x32 frames, 10x10 jittered raster, 128x128 object,
             noise-free
-  config 1  5 Hermite-Gaussian modes, 128x128 frames, 2500-point Fermat spiral,
+  multimode_spiral_128    5 Hermite-Gaussian modes, 128x128 frames, 2500-point Fermat spiral,
             1024x1024 object, Poisson noise at 1e5 photons per frame
-  config 2  fly scan: 256x256 frames, 100x100 raster, 3072x3072 object, 8
+  flyscan_raster_256      fly scan: 256x256 frames, 100x100 raster, 3072x3072 object, 8
             sub-positions of motion blur, Poisson noise at 1e6 photons/frame,
             reconstructed with 8 modes (Section II: fly-scan blur read as
             incoherent illumination)
-  config 4  16 scans of 200-3000 frames, 3 modes, 128x128 frames, 1024^2 objects
+  uneven_spirals_128      16 scans of 200-3000 frames, 3 modes, 128x128 frames, 1024^2 objects
 The paper measured real beamline data that is not available; these seeded
 scans stand in for it.
 """
@@ -269,7 +269,7 @@ def cold_start(f: int, n_modes: int, mean_frame_sum: float, rng,
 # --------------------------------------------------------------------------
 # the workloads
 # --------------------------------------------------------------------------
-def config0(seed: int = 0) -> Scan:
+def single_mode_raster_32(seed: int = 0) -> Scan:
     """Single mode, 32x32 frames, 10x10 raster (step 8 px, origin 12 px,
     U(-1,1) px jitter), 128x128 object, noise-free intensities."""
     r = streams(seed)
@@ -283,7 +283,7 @@ def config0(seed: int = 0) -> Scan:
     P0, O0 = cold_start(f, 1, float(np.mean(np.sum(I, axis=(1, 2)))), r[3],
                         env, [1.0], (h, h))
     return Scan(I, pos, P0, O0, 0.8, P.astype(np.complex64),
-                O.astype(np.complex64), "config0")
+                O.astype(np.complex64), "single_mode_raster_32")
 
 
 HG_ORDERS = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1)]
@@ -310,14 +310,14 @@ def spiral_scan(seed: int, n_frames: int, n_modes: int, weights,
                 O.astype(np.complex64), name)
 
 
-def config1(seed: int = 1, n_frames: int = 2500) -> Scan:
+def multimode_spiral_128(seed: int = 1, n_frames: int = 2500) -> Scan:
     """5 HG modes (weights 1, .5, .25, .12, .06), 128x128 frames, 2500-point
     Fermat spiral (mean step 10 px), 1024x1024 object, 1e5 photons/frame."""
     return spiral_scan(seed, n_frames, 5, [1.0, 0.5, 0.25, 0.12, 0.06],
-                       name="config1")
+                       name="multimode_spiral_128")
 
 
-def config2(seed: int = 2, n_frames: int = 10000, n_modes: int = 8,
+def flyscan_raster_256(seed: int = 2, n_frames: int = 10000, n_modes: int = 8,
             obj: int = 3072, sub_positions: int = 8) -> Scan:
     """Fly scan: 256x256 frames on a 100x100 raster (step 12 px, origin
     814 px), 3072x3072 object, HG00 source probe (waist 32 px, quadratic
@@ -342,22 +342,22 @@ def config2(seed: int = 2, n_frames: int = 10000, n_modes: int = 8,
     P0, O0 = cold_start(f, n_modes, float(np.mean(np.sum(I, axis=(1, 2)))),
                         r[3], env, weights, (obj, obj))
     return Scan(I, pos, P0, O0, 0.8, probes.astype(np.complex64),
-                O.astype(np.complex64), "config2")
+                O.astype(np.complex64), "flyscan_raster_256")
 
 
-def config4_sizes(seed: int = 1000, n_scans: int = 16, lo: int = 200,
+def uneven_scan_sizes(seed: int = 1000, n_scans: int = 16, lo: int = 200,
                   hi: int = 3000):
     rng = streams(seed, 1)[0]
     return [int(v) for v in rng.integers(lo, hi + 1, size=n_scans)]
 
 
-def config4(seed: int = 1000, n_scans: int = 16, sizes=None):
+def uneven_spirals_128(seed: int = 1000, n_scans: int = 16, sizes=None):
     """16 scans of uneven size N_s ~ U{200..3000}, 3 HG modes (weights 1,
     .5, .25), 128x128 frames, 1024^2 objects, Fermat spirals, 1e5 photons."""
     if sizes is None:
-        sizes = config4_sizes(seed, n_scans)
+        sizes = uneven_scan_sizes(seed, n_scans)
     return [spiral_scan(seed + 1 + s, n, 3, [1.0, 0.5, 0.25],
-                        name=f"config4.scan{s}") for s, n in enumerate(sizes)]
+                        name=f"uneven_spirals_128.scan{s}") for s, n in enumerate(sizes)]
 
 
 # --------------------------------------------------------------------------
@@ -365,10 +365,13 @@ def config4(seed: int = 1000, n_scans: int = 16, sizes=None):
 # --------------------------------------------------------------------------
 def random_case(seed: int, n_frames: int, frame: int, n_modes: int,
                 obj_h: int, obj_w: int, consistent: bool = False,
-                beta: float = 0.8) -> dict:
+                beta: float = 0.8, perturb: Optional[float] = None) -> dict:
     """A small random state (psi, P, O) with random positions and positive
     intensities.  With consistent=True the intensities and psi are exactly
-    those of (P, O), i.e. a fixed point of the reconstruction."""
+    those of (P, O), i.e. a fixed point of the reconstruction.  With
+    `perturb`, psi is the exit wave of (P, O) plus complex Gaussian noise of
+    that relative size (a state near the physical one, whose overlap
+    updates are well conditioned)."""
     r = streams(seed)
     P = (r[0].standard_normal((n_modes, frame, frame))
          + 1j * r[0].standard_normal((n_modes, frame, frame)))
@@ -381,6 +384,12 @@ def random_case(seed: int, n_frames: int, frame: int, n_modes: int,
     if consistent:
         psi = P[None] * _windows(O, pos, frame)[:, None]
         I = far_field_intensity(P, O, pos)
+    elif perturb is not None:
+        ex = P[None] * _windows(O, pos, frame)[:, None]
+        noise = (r[4].standard_normal(ex.shape) + 1j * r[4].standard_normal(ex.shape))
+        psi = ex + perturb * np.abs(ex) * noise
+        I = far_field_intensity(P, O, pos) * r[5].uniform(
+            0.5, 1.5, size=(n_frames, frame, frame))
     else:
         psi = (r[4].standard_normal((n_frames, n_modes, frame, frame))
                + 1j * r[4].standard_normal((n_frames, n_modes, frame, frame)))

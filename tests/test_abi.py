@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/dm.h declares, sizes workspaces, and rejects bad input with the
+documented status code before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1808_10375_amd import dm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(dm.LIB_PATH),
+                                reason="libdm.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(dm_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(dm.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(dm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(dm.dm_desc) == 32
+    assert ctypes.sizeof(dm.dm_errors) == 80
+
+
+def desc(**kw):
+    base = dict(n_frames=10, frame=32, n_modes=2, obj_h=100, obj_w=90, beta=0.8)
+    base.update(kw)
+    return dm.make_desc(**base)
+
+
+def test_workspace_bytes_valid_and_invalid():
+    n = dm.dm_workspace_bytes(desc())
+    psi = 10 * 2 * 32 * 32 * 8
+    assert n > psi
+    assert dm.dm_workspace_bytes(desc(n_frames=20)) > n
+    for bad in (dict(frame=48), dict(frame=8), dict(frame=512), dict(n_modes=0),
+                dict(n_modes=17), dict(beta=1.5), dict(beta=-0.1), dict(obj_h=16),
+                dict(n_frames=0), dict(precision=7), dict(flags=4)):
+        assert dm.dm_workspace_bytes(desc(**bad)) == 0, bad
+    # F = 256 needs the multi-pass spectrum buffer as well
+    d256 = desc(frame=256, obj_h=300, obj_w=300)
+    assert dm.dm_workspace_bytes(d256) > 2 * 10 * 2 * 256 * 256 * 8
+
+
+def _init_status(d, pos, ws_bytes=None, ptrs=(256, 256, 256, 256)):
+    L = dm.lib()
+    ctx = ctypes.c_void_p()
+    pos = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
+    ws = dm.dm_workspace_bytes(d) if ws_bytes is None else ws_bytes
+    st = L.dm_init(ctypes.byref(ctx), ctypes.byref(d), ptrs[0],
+                   pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptrs[1], ptrs[2],
+                   ptrs[3], ws, None)
+    assert not ctx.value
+    return st, dm.dm_last_error(None)
+
+
+def test_init_rejects_out_of_bounds_positions():
+    d = desc()
+    pos = np.zeros((10, 2), np.int32)
+    pos[3] = (100 - 32 + 1, 0)
+    st, msg = _init_status(d, pos)
+    assert st == dm.DM_E_BOUNDS and "view 3" in msg
+    pos[3] = (0, -1)
+    assert _init_status(d, pos)[0] == dm.DM_E_BOUNDS
+
+
+def test_init_rejects_small_workspace_and_bad_pointers():
+    d = desc()
+    pos = np.zeros((10, 2), np.int32)
+    assert _init_status(d, pos, ws_bytes=dm.dm_workspace_bytes(d) - 1)[0] == dm.DM_E_WORKSPACE
+    assert _init_status(d, pos, ptrs=(0, 256, 256, 256))[0] == dm.DM_E_ARG
+    assert _init_status(d, pos, ptrs=(260, 256, 256, 256))[0] == dm.DM_E_ARG  # misaligned I
+    assert _init_status(d, pos, ptrs=(256, 256, 256, 264))[0] == dm.DM_E_ARG  # workspace
+    assert _init_status(desc(frame=24), pos)[0] == dm.DM_E_UNSUPPORTED
+    assert _init_status(desc(beta=2.0), pos)[0] == dm.DM_E_ARG
+    assert _init_status(desc(precision=dm.DM_BF16X3_DFT, frame=64), pos)[0] \
+        == dm.DM_E_UNSUPPORTED
+
+
+def test_calls_on_null_context():
+    L = dm.lib()
+    assert L.dm_iterate(None, 1) == dm.DM_E_ARG
+    assert L.dm_error(None, ctypes.byref(dm.dm_errors())) == dm.DM_E_ARG
+    assert L.dm_iterations(None) == -1
+    L.dm_free(None)
+    for s in range(0, -8, -1):
+        assert dm.dm_status_str(s).startswith("DM_")

@@ -298,7 +298,7 @@ def test_run_starts_from_product_views():
 def test_noise_free_reconstruction_converges_small_scan():
     """Sanity (not a parity gate): on a small noise-free scan, err = eps_P
     falls steadily from its first value."""
-    s = synth.config0(0)
+    s = synth.single_mode_raster_32(0)
     _, _, _, hist = dm.run(s.P0, s.O0, s.pos, s.I, 0.8, 12)
     errs = [h["eps_probe"] for h in hist]
     assert all(np.isfinite(errs))

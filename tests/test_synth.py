@@ -24,15 +24,15 @@ def test_hermite_gauss_modes_orthogonal_with_weights():
     assert np.allclose(np.real(np.diag(g)), w, rtol=1e-12)
 
 
-def test_config0_shapes_and_bounds():
-    s = synth.config0(0)
+def test_single_mode_raster_shapes_and_bounds():
+    s = synth.single_mode_raster_32(0)
     assert s.I.shape == (100, 32, 32) and s.I.dtype == np.float32
     assert s.P0.shape == (1, 32, 32) and s.O0.shape == (128, 128)
     assert s.pos.min() >= 0 and s.pos.max() <= 128 - 32
     # noise-free: intensities are exactly |FFT(P O)|^2 of the true fields
     assert np.all(s.I >= 0)
     # deterministic
-    assert np.array_equal(synth.config0(0).I, s.I)
+    assert np.array_equal(synth.single_mode_raster_32(0).I, s.I)
 
 
 def test_fermat_spiral_step_and_bounds():
@@ -55,11 +55,11 @@ def test_poisson_budget_small_spiral():
     assert abs(tot / mean - 1.0) < 1e-5
 
 
-def test_config4_sizes_in_range():
-    sizes = synth.config4_sizes()
+def test_uneven_scan_sizes_in_range():
+    sizes = synth.uneven_scan_sizes()
     assert len(sizes) == 16 and min(sizes) >= 200 and max(sizes) <= 3000
 
 
-def test_config2_strip_positions_in_bounds():
+def test_flyscan_strip_positions_in_bounds():
     full = synth.raster_positions(100, 100, 12.0, 814.0)
     assert full.min() >= 0 and full.max() <= 3072 - 256

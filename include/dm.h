@@ -87,6 +87,12 @@ typedef enum {
                                     context's stream (read by
                                     dm_phase_times)                          */
 
+#define DM_FLAG_GRAPH 4u         /* capture one iteration's launches (all
+                                    scans) into a hipGraph at the first
+                                    dm_iterate and replay it once per
+                                    iteration; needs a non-NULL stream and
+                                    excludes DM_FLAG_PHASE_TIMING           */
+
 /* Phases of one iteration, in launch order (indices of dm_phase_times). */
 #define DM_PHASE_VIEWS 0         /* Eq. 3 with F_c: exit waves, transforms,
                                     modulus projection, view update         */
@@ -108,6 +114,22 @@ typedef struct {
 } dm_desc;
 
 #define DM_MAX_MODES 16
+#define DM_MAX_PROBE_CHUNKS 64
+
+/* Launch shapes chosen per context (dm_set_tuning / dm_autotune).  They
+ * change the speed of an iteration and the summation order of the probe
+ * sums (results agree to rounding), nothing else. */
+typedef struct {
+  int32_t obj_tile;      /* edge of the object tiles of the Eq. 5 gather:
+                            16 or 32                                      */
+  int32_t probe_chunks;  /* runs of views summed separately in the Eq. 4
+                            partial sums, 1..DM_MAX_PROBE_CHUNKS (capped at
+                            each scan's view count)                       */
+  int32_t multipass;     /* 1: three-kernel transform path; only where the
+                            workspace holds its spectrum buffer (F = 256 or
+                            DM_FLAG_MULTIPASS at init); forced for F = 256 */
+  int32_t reserved;      /* must be 0                                     */
+} dm_tuning;
 
 typedef struct {
   int32_t iter;        /* 1-based index of the iteration these belong to  */
@@ -181,6 +203,46 @@ dm_status dm_set_state(dm_ctx* ctx, const void* psi_dev, const void* probe_dev,
  * iterations enqueued since the previous call, and to *n_iter_host their
  * number; the accumulators restart.  Without the flag: DM_E_STATE. */
 dm_status dm_phase_times(dm_ctx* ctx, double* ms_host, int32_t* n_iter_host);
+
+/* ---- batches: many scans, one launch chain per iteration ------------------
+ * All scans of a batch share F, M, precision and flags; each has its own
+ * views, positions, intensities, probe, object, beta and error ring.  One
+ * dm_iterate advances every scan by one DM iteration with one launch per
+ * phase for the whole batch (one graph launch with DM_FLAG_GRAPH).  The
+ * single-scan calls above act on scan 0; dm_get_state/dm_set_state need a
+ * batch of one. */
+size_t dm_batch_workspace_bytes(int32_t n_scans, const dm_desc* descs);
+
+/* Like dm_init for n_scans scans; arrays of n_scans pointers (I, positions,
+ * probe0, object0 per scan); one workspace for the batch. */
+dm_status dm_batch_init(dm_ctx** out, int32_t n_scans, const dm_desc* descs,
+                        const float* const* I_devs, const int32_t* const* pos_hosts,
+                        const void* const* probe0_devs,
+                        const void* const* object0_devs, void* workspace_dev,
+                        size_t workspace_bytes, void* hip_stream);
+
+int32_t dm_n_scans(const dm_ctx* ctx);
+dm_status dm_scan_get_object(dm_ctx* ctx, int32_t scan, void* dst_dev);
+dm_status dm_scan_get_probe(dm_ctx* ctx, int32_t scan, void* dst_dev);
+dm_status dm_scan_error_history(dm_ctx* ctx, int32_t scan, int32_t first,
+                                int32_t count, dm_errors* out_host);
+
+/* ---- launch tuning -------------------------------------------------------- */
+dm_status dm_get_tuning(const dm_ctx* ctx, dm_tuning* out);
+
+/* Apply a tuning (re-uploads the object tile lists; synchronises). */
+dm_status dm_set_tuning(dm_ctx* ctx, const dm_tuning* tuning);
+
+/* Time every candidate tuning (object tile 16/32, probe chunks
+ * {1/2, 1, 2} x default, transform path where available) over `reps`
+ * iterations each (median of per-iteration HIP-event times, ties to the
+ * smaller tile), apply the fastest and write it to *out.  With cache_path,
+ * a previous result for the same (GPU architecture, F, M, view-count bucket,
+ * scan count) is read from that JSON-lines file instead, and a new result is
+ * appended to it.  The timed iterations advance the state; afterwards the
+ * state is rebuilt from probe0/object0 as at init, so call it right after
+ * init, while those buffers are still alive and unchanged.  Synchronises. */
+dm_status dm_autotune(dm_ctx* ctx, int32_t reps, const char* cache_path, dm_tuning* out);
 
 /* Release the host-side context.  Does not touch the caller's buffers.
  * NULL is a no-op. */

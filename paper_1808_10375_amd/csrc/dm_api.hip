@@ -1,7 +1,8 @@
 // dm_api.hip -- host side of libdm: the C-ABI declared in include/dm.h.
-// Validation, workspace carving, the object-tile -> view lists, and the
-// launch sequence of one difference-map iteration (Section II, Eqs. 2-6 of
-// arXiv:1808.10375).
+// Validation, workspace carving, object-tile -> view lists, spatial view
+// order, the launch chain of one difference-map iteration (Section II,
+// Eqs. 2-6 of arXiv:1808.10375) for a batch of scans, its hipGraph capture,
+// and the launch-shape autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +17,7 @@
 #include "dm_kernels.hpp"
 
 using dmk::DevErrors;
+using dmk::ScanDev;
 static_assert(sizeof(DevErrors) == sizeof(dm_errors), "error record layout");
 
 namespace {
@@ -24,57 +26,67 @@ thread_local std::string g_init_error;
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// Which transform path a descriptor uses.
-bool use_fused(const dm_desc& d) {
-  return d.frame <= 128 && !(d.flags & DM_FLAG_MULTIPASS);
+// ---------------------------------------------------------------------------
+// launch shapes
+// ---------------------------------------------------------------------------
+int n_pblk(int F) { return (F * F + 255) / 256; }
+
+int default_chunks(int F) {
+  int C = (2048 + n_pblk(F) - 1) / n_pblk(F);
+  return std::max(1, std::min(C, DM_MAX_PROBE_CHUNKS));
 }
 
-struct Layout {
-  size_t psi, opart, tspec, gscr, P, O, D, num_part, den_part, err_psi, err_obj, err_probe,
-      ring, counter, pos, order, tile_ptr, tile_views, tw, total;
-  int tile, tiles_x, tiles_y, ntiles, nnz_max, C, chunk, n_psi_parts, n_pblk, cb;
-};
-
-// Object tile edge of the gather kernel.
-constexpr int kObjTile = 16;
-
-int probe_chunks(const dm_desc& d) {
-  const int FF = d.frame * d.frame;
-  const int pix_blocks = (FF + 255) / 256;
-  int C = (2048 + pix_blocks - 1) / pix_blocks;
-  C = std::max(1, std::min(C, d.n_frames));
-  return C;
+bool has_spectrum_buffer(const dm_desc& d) {
+  return d.frame == 256 || (d.flags & DM_FLAG_MULTIPASS);
 }
 
-int cols_per_block(const dm_desc& d) {
-  const int B = d.frame / 16;
-  int cb = 1024 / (B * d.n_modes);
+dm_tuning default_tuning(const dm_desc& d) {
+  dm_tuning t{};
+  t.obj_tile = 16;
+  t.probe_chunks = default_chunks(d.frame);
+  t.multipass = has_spectrum_buffer(d) ? 1 : 0;
+  return t;
+}
+
+int cols_per_block(int F, int M) {
+  const int B = F / 16;
+  int cb = 1024 / (B * M);
   int p = 1;
   while (p * 2 <= cb && p * 2 <= 16) p *= 2;
   return p;
 }
 
-Layout make_layout(const dm_desc& d) {
-  Layout L{};
+int row_block(int F) {
+  const int B = F / 16;
+  return std::min(256 / B, F);
+}
+
+// ---------------------------------------------------------------------------
+// workspace carving: a context header, then one region per scan
+// ---------------------------------------------------------------------------
+struct ScanLayout {
+  size_t psi, opart, gscr, tspec, P, O, D, num_part, den_part, err_psi, err_obj, err_probe,
+      ring, counter, pos, order, tile_ptr, tile_views, bytes;
+  int ntiles16, nnz16, n_psi_parts_fused, n_psi_parts_multi;
+};
+
+int tiles_for(int H, int W, int T) { return ((H + T - 1) / T) * ((W + T - 1) / T); }
+
+int nnz_bound(const dm_desc& d, int T) {
+  const int span = d.frame / T + 1 + (d.frame % T ? 1 : 0);
+  return d.n_frames * span * span;
+}
+
+ScanLayout scan_layout(const dm_desc& d) {
+  ScanLayout L{};
   const size_t N = d.n_frames, M = d.n_modes, F = d.frame, FF = F * F;
-  const size_t c8 = 8;  // complex64 bytes
-  L.tile = kObjTile;
-  L.tiles_x = (d.obj_w + L.tile - 1) / L.tile;
-  L.tiles_y = (d.obj_h + L.tile - 1) / L.tile;
-  L.ntiles = L.tiles_x * L.tiles_y;
-  const int span = (int)(F / L.tile) + 1 + (F % L.tile ? 1 : 0);
-  L.nnz_max = (int)N * span * span;
-  L.C = probe_chunks(d);
-  L.chunk = (int)((N + L.C - 1) / L.C);
-  L.n_pblk = (int)((FF + 255) / 256);
-  const bool fused = use_fused(d);
-  const int B = (int)F / 16;
-  const int rb = std::min(256 / B, (int)F);
-  L.n_psi_parts = fused ? (int)N : (int)N * ((int)F / rb);
-  L.cb = fused ? 0 : cols_per_block(d);
+  const size_t c8 = 8;
+  L.ntiles16 = tiles_for(d.obj_h, d.obj_w, 16);  // the larger of the two tile counts
+  L.nnz16 = std::max(nnz_bound(d, 16), nnz_bound(d, 32));
+  L.n_psi_parts_fused = (int)N;
+  L.n_psi_parts_multi = (int)N * ((int)F / row_block((int)F));
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -83,25 +95,60 @@ Layout make_layout(const dm_desc& d) {
   };
   L.psi = take(N * M * FF * c8);
   L.opart = take(N * FF * c8);
-  L.tspec = fused ? 0 : take(N * M * FF * c8);
-  L.gscr = fused ? take(N * FF * 4) : 0;
+  L.gscr = d.frame <= 128 ? take(N * FF * 4) : 0;
+  L.tspec = has_spectrum_buffer(d) ? take(N * M * FF * c8) : 0;
   L.P = take(M * FF * c8);
   L.O = take((size_t)d.obj_h * d.obj_w * c8);
   L.D = take(FF * 4);
-  L.num_part = take((size_t)L.C * M * FF * c8);
-  L.den_part = take((size_t)L.C * FF * 4);
-  L.err_psi = take((size_t)L.n_psi_parts * 2 * 4);
-  L.err_obj = take((size_t)L.ntiles * 2 * 4);
-  L.err_probe = take((size_t)L.n_pblk * M * 2 * 4);
+  L.num_part = take((size_t)DM_MAX_PROBE_CHUNKS * M * FF * c8);
+  L.den_part = take((size_t)DM_MAX_PROBE_CHUNKS * FF * 4);
+  L.err_psi = take((size_t)std::max(L.n_psi_parts_fused, L.n_psi_parts_multi) * 2 * 4);
+  L.err_obj = take((size_t)L.ntiles16 * 2 * 4);
+  L.err_probe = take((size_t)n_pblk((int)F) * M * 2 * 4);
   L.ring = take(sizeof(DevErrors) * dmk::kRing);
-  L.counter = take(2 * sizeof(int));  // [0] iteration counter, [1] flags
+  L.counter = take(sizeof(int));
   L.pos = take(N * 2 * 4);
   L.order = take(N * 4);
-  L.tile_ptr = take(((size_t)L.ntiles + 1) * 4);
-  L.tile_views = take((size_t)L.nnz_max * 4);
-  L.tw = take(F * c8);
-  L.total = off;
+  L.tile_ptr = take(((size_t)L.ntiles16 + 1) * 4);
+  L.tile_views = take((size_t)L.nnz16 * 4);
+  L.bytes = off;
   return L;
+}
+
+struct CtxLayout {
+  size_t scans, vmap, tmap, cmap, tw, flags, header;
+  std::vector<size_t> scan_base;
+  std::vector<ScanLayout> sl;
+  size_t total;
+};
+
+CtxLayout ctx_layout(int n_scans, const dm_desc* d) {
+  CtxLayout C{};
+  size_t views = 0, tiles = 0;
+  for (int s = 0; s < n_scans; ++s) {
+    views += d[s].n_frames;
+    tiles += tiles_for(d[s].obj_h, d[s].obj_w, 16);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  C.scans = take(sizeof(ScanDev) * n_scans);
+  C.vmap = take(sizeof(int2) * views);
+  C.tmap = take(sizeof(int2) * tiles);
+  C.cmap = take(sizeof(int2) * (size_t)DM_MAX_PROBE_CHUNKS * n_scans);
+  C.tw = take(sizeof(float2) * d[0].frame);
+  C.flags = take(sizeof(int));
+  C.header = off;
+  for (int s = 0; s < n_scans; ++s) {
+    C.sl.push_back(scan_layout(d[s]));
+    C.scan_base.push_back(off);
+    off = align_up(off + C.sl.back().bytes);
+  }
+  C.total = off;
+  return C;
 }
 
 dm_status validate_desc(const dm_desc* d, std::string& why) {
@@ -123,8 +170,12 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     why = "the BF16x3 DFT form is not built into this library";
     return DM_E_UNSUPPORTED;
   }
-  if (d->flags & ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING)) {
+  if (d->flags & ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH)) {
     why = "unknown flag bits";
+    return DM_E_ARG;
+  }
+  if ((d->flags & DM_FLAG_GRAPH) && (d->flags & DM_FLAG_PHASE_TIMING)) {
+    why = "DM_FLAG_GRAPH and DM_FLAG_PHASE_TIMING exclude each other";
     return DM_E_ARG;
   }
   if ((double)d->obj_h * d->obj_w * 8.0 >= 2147483648.0) {
@@ -132,55 +183,82 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     return DM_E_UNSUPPORTED;
   }
   if ((double)d->n_frames * d->frame * d->frame >= 2147483648.0) {
-    why = "more than 2^31 detector pixels in total";
+    why = "more than 2^31 detector pixels in one scan";
     return DM_E_UNSUPPORTED;
+  }
+  return DM_OK;
+}
+
+dm_status validate_batch(int n_scans, const dm_desc* d, std::string& why) {
+  if (n_scans < 1 || !d) { why = "need at least one scan"; return DM_E_ARG; }
+  for (int s = 0; s < n_scans; ++s) {
+    dm_status st = validate_desc(&d[s], why);
+    if (st != DM_OK) {
+      if (n_scans > 1) why = "scan " + std::to_string(s) + ": " + why;
+      return st;
+    }
+    if (d[s].frame != d[0].frame || d[s].n_modes != d[0].n_modes ||
+        d[s].precision != d[0].precision || d[s].flags != d[0].flags) {
+      why = "all scans of a batch need the same frame, n_modes, precision and flags";
+      return DM_E_ARG;
+    }
   }
   return DM_OK;
 }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
 struct dm_ctx {
-  dm_desc d;
-  Layout L;
-  hipStream_t stream;
-  char* ws;
-  const float* I;
+  struct Scan {
+    dm_desc d;
+    ScanLayout L;
+    size_t base;
+    const float* I;
+    const void* P0;  // caller's initial guesses (used again only by dm_autotune)
+    const void* O0;
+    std::vector<int> pos, order;
+    int C = 1, chunk = 1, ntiles = 0, tiles_x = 0;
+  };
+  std::vector<Scan> scans;
+  CtxLayout CL;
+  int F = 0, M = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
   bool failed = false;
   std::string err;
   int iters = 0;
-  std::vector<int> pos_host;
-  // phase timing: event pairs recorded since the last dm_phase_times
+  int total_views = 0, total_tiles = 0, total_chunks = 0;
+  dm_tuning tune{};
+  // graph of one iteration
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  // phase timing
   struct Mark { int phase; hipEvent_t a, b; };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> event_pool;
   int timed_iters = 0;
+
   ~dm_ctx() {
     for (auto& m : marks) { event_pool.push_back(m.a); event_pool.push_back(m.b); }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
-  bool timing() const { return (d.flags & DM_FLAG_PHASE_TIMING) != 0; }
-
-  float2* psi() { return reinterpret_cast<float2*>(ws + L.psi); }
-  float2* opart() { return reinterpret_cast<float2*>(ws + L.opart); }
-  float2* tspec() { return reinterpret_cast<float2*>(ws + L.tspec); }
-  float* gscr() { return reinterpret_cast<float*>(ws + L.gscr); }
-  int* order() { return reinterpret_cast<int*>(ws + L.order); }
-  float2* P() { return reinterpret_cast<float2*>(ws + L.P); }
-  float2* O() { return reinterpret_cast<float2*>(ws + L.O); }
-  float* D() { return reinterpret_cast<float*>(ws + L.D); }
-  float2* num_part() { return reinterpret_cast<float2*>(ws + L.num_part); }
-  float* den_part() { return reinterpret_cast<float*>(ws + L.den_part); }
-  float* err_psi() { return reinterpret_cast<float*>(ws + L.err_psi); }
-  float* err_obj() { return reinterpret_cast<float*>(ws + L.err_obj); }
-  float* err_probe() { return reinterpret_cast<float*>(ws + L.err_probe); }
-  DevErrors* ring() { return reinterpret_cast<DevErrors*>(ws + L.ring); }
-  int* counter() { return reinterpret_cast<int*>(ws + L.counter); }
-  int* flags() { return reinterpret_cast<int*>(ws + L.counter) + 1; }
-  int* pos() { return reinterpret_cast<int*>(ws + L.pos); }
-  int* tile_ptr() { return reinterpret_cast<int*>(ws + L.tile_ptr); }
-  int* tile_views() { return reinterpret_cast<int*>(ws + L.tile_views); }
-  float2* tw() { return reinterpret_cast<float2*>(ws + L.tw); }
+  bool timing() const { return (flags & DM_FLAG_PHASE_TIMING) != 0; }
+  template <class T>
+  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+  template <class T>
+  T* sat(int s, size_t off) { return reinterpret_cast<T*>(ws + scans[s].base + off); }
+  ScanDev* scan_dev() { return at<ScanDev>(CL.scans); }
+  int2* vmap() { return at<int2>(CL.vmap); }
+  int2* tmap() { return at<int2>(CL.tmap); }
+  int2* cmap() { return at<int2>(CL.cmap); }
+  float2* tw() { return at<float2>(CL.tw); }
+  int* flags_dev() { return at<int>(CL.flags); }
 };
 
 namespace {
@@ -191,16 +269,22 @@ dm_status fail_hip(dm_ctx* c, hipError_t e, const char* where) {
   return DM_E_HIP;
 }
 
-#define DM_HIP(ctx, call)                                   \
-  do {                                                      \
-    hipError_t e_ = (call);                                 \
+#define DM_HIP(ctx, call)                                    \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
     if (e_ != hipSuccess) return fail_hip((ctx), e_, #call); \
   } while (0)
 
-#define DM_LAUNCHED(ctx, name)                                  \
-  do {                                                          \
-    hipError_t e_ = hipGetLastError();                          \
-    if (e_ != hipSuccess) return fail_hip((ctx), e_, name);     \
+#define DM_LAUNCHED(ctx, name)                              \
+  do {                                                      \
+    hipError_t e_ = hipGetLastError();                      \
+    if (e_ != hipSuccess) return fail_hip((ctx), e_, name); \
+  } while (0)
+
+#define DM_TRY(expr)            \
+  do {                          \
+    dm_status s_ = (expr);      \
+    if (s_ != DM_OK) return s_; \
   } while (0)
 
 dm_status check_ctx(dm_ctx* c) {
@@ -220,58 +304,33 @@ std::vector<float2> twiddles(int F) {
   return t;
 }
 
-// Lists of views whose window meets each object tile, ascending view order.
-void build_tile_lists(const dm_desc& d, const Layout& L, const int* pos, std::vector<int>& ptr,
-                      std::vector<int>& views) {
-  const int T = L.tile, F = d.frame;
-  std::vector<int> count(L.ntiles, 0);
+// Lists of views whose window meets each T x T object tile, ascending view
+// order.
+void build_tile_lists(const dm_desc& d, int T, const std::vector<int>& pos,
+                      std::vector<int>& ptr, std::vector<int>& views) {
+  const int F = d.frame;
+  const int tx_n = (d.obj_w + T - 1) / T, ty_n = (d.obj_h + T - 1) / T;
+  const int ntiles = tx_n * ty_n;
+  std::vector<int> count(ntiles, 0);
   for (int j = 0; j < d.n_frames; ++j) {
     const int y = pos[2 * j], x = pos[2 * j + 1];
     for (int ty = y / T; ty <= (y + F - 1) / T; ++ty)
-      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx) count[ty * L.tiles_x + tx]++;
+      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx) count[ty * tx_n + tx]++;
   }
-  ptr.assign(L.ntiles + 1, 0);
-  for (int i = 0; i < L.ntiles; ++i) ptr[i + 1] = ptr[i] + count[i];
-  views.assign(std::max(ptr[L.ntiles], 1), 0);
+  ptr.assign(ntiles + 1, 0);
+  for (int i = 0; i < ntiles; ++i) ptr[i + 1] = ptr[i] + count[i];
+  views.assign(std::max(ptr[ntiles], 1), 0);
   std::vector<int> fill(ptr.begin(), ptr.end() - 1);
   for (int j = 0; j < d.n_frames; ++j) {
     const int y = pos[2 * j], x = pos[2 * j + 1];
     for (int ty = y / T; ty <= (y + F - 1) / T; ++ty)
-      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx) views[fill[ty * L.tiles_x + tx]++] = j;
+      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx) views[fill[ty * tx_n + tx]++] = j;
   }
-}
-
-hipError_t take_event(dm_ctx* c, hipEvent_t* e) {
-  if (!c->event_pool.empty()) {
-    *e = c->event_pool.back();
-    c->event_pool.pop_back();
-    return hipSuccess;
-  }
-  return hipEventCreate(e);
-}
-
-// Record the start of a timed phase; returns the index of its mark or -1.
-dm_status phase_begin(dm_ctx* c, int phase, int* idx) {
-  *idx = -1;
-  if (!c->timing()) return DM_OK;
-  dm_ctx::Mark m{phase, nullptr, nullptr};
-  DM_HIP(c, take_event(c, &m.a));
-  DM_HIP(c, take_event(c, &m.b));
-  DM_HIP(c, hipEventRecord(m.a, c->stream));
-  c->marks.push_back(m);
-  *idx = (int)c->marks.size() - 1;
-  return DM_OK;
-}
-
-dm_status phase_end(dm_ctx* c, int idx) {
-  if (idx < 0) return DM_OK;
-  DM_HIP(c, hipEventRecord(c->marks[idx].b, c->stream));
-  return DM_OK;
 }
 
 // Views sorted along a Z-order curve of their window corners: runs of
 // consecutive entries cover compact patches of the object.
-std::vector<int> spatial_order(const dm_desc& d, const int* pos) {
+std::vector<int> spatial_order(const dm_desc& d, const std::vector<int>& pos) {
   auto spread = [](uint32_t v) {
     uint64_t x = v & 0xffffu;
     x = (x | (x << 8)) & 0x00ff00ffu;
@@ -291,112 +350,6 @@ std::vector<int> spatial_order(const dm_desc& d, const int* pos) {
   return order;
 }
 
-template <int F>
-dm_status launch_fourier_fused(dm_ctx* c) {
-  const dm_desc& d = c->d;
-  hipLaunchKernelGGL(dmk::k_fourier_fused<F>, dim3(d.n_frames), dim3(F * F / 16), 0, c->stream,
-                     c->psi(), c->I, c->P(), c->O(), c->pos(), c->order(), c->tw(), c->opart(),
-                     c->gscr(), c->err_psi(), d.n_frames, d.n_modes, d.obj_h, d.obj_w, d.beta);
-  DM_LAUNCHED(c, "k_fourier_fused");
-  return DM_OK;
-}
-
-template <int F>
-dm_status launch_fourier_multipass(dm_ctx* c) {
-  const dm_desc& d = c->d;
-  constexpr int B = F / 16, RB = dmk::RowCfg<F>::RB, NT = dmk::RowCfg<F>::NT;
-  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(d.n_frames * d.n_modes, F / RB), dim3(NT), 0,
-                     c->stream, c->psi(), c->P(), c->O(), c->pos(), c->tw(), c->tspec(),
-                     d.n_modes, d.obj_w);
-  DM_LAUNCHED(c, "k_rows_fwd");
-  const int cb = c->L.cb;
-  const size_t lds = (size_t)cb * d.n_modes * (F + 1) * sizeof(float2);
-  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(d.n_frames, F / cb), dim3(cb * B * d.n_modes), lds,
-                     c->stream, c->tspec(), c->I, c->tw(), d.n_modes, cb);
-  DM_LAUNCHED(c, "k_cols");
-  hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(d.n_frames, F / RB), dim3(NT), 0, c->stream,
-                     c->psi(), c->P(), c->O(), c->pos(), c->tw(), c->tspec(), c->opart(),
-                     c->err_psi(), d.n_modes, d.obj_w, d.beta);
-  DM_LAUNCHED(c, "k_rows_inv");
-  return DM_OK;
-}
-
-dm_status launch_views(dm_ctx* c) {
-  const int F = c->d.frame;
-  if (use_fused(c->d)) {
-    switch (F) {
-      case 16: return launch_fourier_fused<16>(c);
-      case 32: return launch_fourier_fused<32>(c);
-      case 64: return launch_fourier_fused<64>(c);
-      case 128: return launch_fourier_fused<128>(c);
-    }
-  } else {
-    switch (F) {
-      case 16: return launch_fourier_multipass<16>(c);
-      case 32: return launch_fourier_multipass<32>(c);
-      case 64: return launch_fourier_multipass<64>(c);
-      case 128: return launch_fourier_multipass<128>(c);
-      case 256: return launch_fourier_multipass<256>(c);
-    }
-  }
-  c->err = "unsupported frame size";
-  return DM_E_UNSUPPORTED;
-}
-
-#define DM_TRY(expr)              \
-  do {                            \
-    dm_status s_ = (expr);        \
-    if (s_ != DM_OK) return s_;   \
-  } while (0)
-
-dm_status launch_iteration(dm_ctx* c) {
-  const dm_desc& d = c->d;
-  const Layout& L = c->L;
-  const int FF = d.frame * d.frame;
-  int mk;
-  DM_TRY(phase_begin(c, DM_PHASE_VIEWS, &mk));
-  DM_TRY(launch_views(c));
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
-  if (L.tile == 16)
-    hipLaunchKernelGGL(dmk::k_object<16>, dim3(L.ntiles), dim3(256), 0, c->stream, c->opart(),
-                       c->D(), c->O(), c->pos(), c->tile_ptr(), c->tile_views(), d.frame,
-                       d.obj_h, d.obj_w, L.tiles_x, c->err_obj());
-  else
-    hipLaunchKernelGGL(dmk::k_object<32>, dim3(L.ntiles), dim3(256), 0, c->stream, c->opart(),
-                       c->D(), c->O(), c->pos(), c->tile_ptr(), c->tile_views(), d.frame,
-                       d.obj_h, d.obj_w, L.tiles_x, c->err_obj());
-  DM_LAUNCHED(c, "k_object");
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_PROBE_PARTIAL, &mk));
-  hipLaunchKernelGGL(dmk::k_probe_partial, dim3(L.n_pblk, L.C), dim3(256), 0, c->stream,
-                     c->psi(), c->O(), c->pos(), c->order(), d.n_frames, d.n_modes, d.frame,
-                     d.obj_w, L.chunk, c->num_part(), c->den_part());
-  DM_LAUNCHED(c, "k_probe_partial");
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_PROBE_FINAL, &mk));
-  hipLaunchKernelGGL(dmk::k_probe_final, dim3(L.n_pblk), dim3(256), 0, c->stream, c->num_part(),
-                     c->den_part(), c->P(), c->D(), L.C, d.n_modes, FF, c->err_probe());
-  DM_LAUNCHED(c, "k_probe_final");
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_ERRORS, &mk));
-  hipLaunchKernelGGL(dmk::k_errors, dim3(1), dim3(256), 0, c->stream, c->err_psi(),
-                     L.n_psi_parts, c->err_obj(), L.ntiles, c->err_probe(), L.n_pblk, d.n_modes,
-                     c->counter(), c->ring(), c->flags());
-  DM_LAUNCHED(c, "k_errors");
-  DM_TRY(phase_end(c, mk));
-  if (c->timing()) c->timed_iters++;
-  return DM_OK;
-}
-
-dm_status refresh_mode_power(dm_ctx* c) {
-  const int FF = c->d.frame * c->d.frame;
-  hipLaunchKernelGGL(dmk::k_mode_power, dim3((FF + 255) / 256), dim3(256), 0, c->stream, c->P(),
-                     c->D(), c->d.n_modes, FF);
-  DM_LAUNCHED(c, "k_mode_power");
-  return DM_OK;
-}
-
 hipError_t set_cols_lds(int F, int bytes) {
   const void* k = nullptr;
   switch (F) {
@@ -409,123 +362,346 @@ hipError_t set_cols_lds(int F, int bytes) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
-
-}  // namespace
-
-extern "C" {
-
-size_t dm_workspace_bytes(const dm_desc* desc) {
-  std::string why;
-  if (validate_desc(desc, why) != DM_OK) return 0;
-  return make_layout(*desc).total;
+// (Re)build everything that depends on the tuning: tile lists, chunking, the
+// scan descriptor table and the block maps; upload them.  Synchronises.
+dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
+  c->tune = t;
+  if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  const int n = (int)c->scans.size();
+  std::vector<ScanDev> sd(n);
+  std::vector<int2> tmap, cmap;
+  // host staging that must outlive the asynchronous copies below
+  std::vector<std::vector<int>> ptrs(n), lists(n);
+  for (int s = 0; s < n; ++s) {
+    auto& S = c->scans[s];
+    const ScanLayout& L = S.L;
+    build_tile_lists(S.d, t.obj_tile, S.pos, ptrs[s], lists[s]);
+    if ((int)lists[s].size() > L.nnz16) {
+      c->err = "internal: tile list larger than its bound";
+      return DM_E_STATE;
+    }
+    S.tiles_x = (S.d.obj_w + t.obj_tile - 1) / t.obj_tile;
+    S.ntiles = (int)ptrs[s].size() - 1;
+    S.C = std::max(1, std::min(t.probe_chunks, S.d.n_frames));
+    S.chunk = (S.d.n_frames + S.C - 1) / S.C;
+    S.C = (S.d.n_frames + S.chunk - 1) / S.chunk;  // no empty chunks
+    DM_HIP(c, hipMemcpyAsync(c->sat<int>(s, L.tile_ptr), ptrs[s].data(),
+                             ptrs[s].size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    DM_HIP(c, hipMemcpyAsync(c->sat<int>(s, L.tile_views), lists[s].data(),
+                             lists[s].size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    ScanDev& v = sd[s];
+    v.psi = c->sat<float2>(s, L.psi);
+    v.I = S.I;
+    v.P = c->sat<float2>(s, L.P);
+    v.O = c->sat<float2>(s, L.O);
+    v.pos = c->sat<int>(s, L.pos);
+    v.order = c->sat<int>(s, L.order);
+    v.opart = c->sat<float2>(s, L.opart);
+    v.gscr = S.d.frame <= 128 ? c->sat<float>(s, L.gscr) : nullptr;
+    v.tspec = L.tspec ? c->sat<float2>(s, L.tspec) : nullptr;
+    v.D = c->sat<float>(s, L.D);
+    v.num_part = c->sat<float2>(s, L.num_part);
+    v.den_part = c->sat<float>(s, L.den_part);
+    v.err_psi = c->sat<float>(s, L.err_psi);
+    v.err_obj = c->sat<float>(s, L.err_obj);
+    v.err_probe = c->sat<float>(s, L.err_probe);
+    v.tile_ptr = c->sat<int>(s, L.tile_ptr);
+    v.tile_views = c->sat<int>(s, L.tile_views);
+    v.counter = c->sat<int>(s, L.counter);
+    v.ring = c->sat<DevErrors>(s, L.ring);
+    v.N = S.d.n_frames;
+    v.H = S.d.obj_h;
+    v.W = S.d.obj_w;
+    v.tiles_x = S.tiles_x;
+    v.ntiles = S.ntiles;
+    v.C = S.C;
+    v.chunk = S.chunk;
+    v.n_psi_parts = t.multipass ? L.n_psi_parts_multi : L.n_psi_parts_fused;
+    v.beta = S.d.beta;
+    v.pad = 0;
+    for (int i = 0; i < S.ntiles; ++i) tmap.push_back(make_int2(s, i));
+    for (int i = 0; i < S.C; ++i) cmap.push_back(make_int2(s, i));
+  }
+  c->total_tiles = (int)tmap.size();
+  c->total_chunks = (int)cmap.size();
+  DM_HIP(c, hipMemcpyAsync(c->scan_dev(), sd.data(), sd.size() * sizeof(ScanDev),
+                           hipMemcpyHostToDevice, c->stream));
+  DM_HIP(c, hipMemcpyAsync(c->tmap(), tmap.data(), tmap.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, c->stream));
+  DM_HIP(c, hipMemcpyAsync(c->cmap(), cmap.data(), cmap.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, c->stream));
+  if (t.multipass) {
+    const int lds =
+        (int)((size_t)cols_per_block(c->F, c->M) * c->M * (c->F + 1) * sizeof(float2));
+    DM_HIP(c, set_cols_lds(c->F, lds));
+  }
+  DM_HIP(c, hipStreamSynchronize(c->stream));
+  return DM_OK;
 }
 
-dm_status dm_init(dm_ctx** out, const dm_desc* desc, const float* I_dev, const int32_t* pos_host,
-                  const void* probe0_dev, const void* object0_dev, void* workspace_dev,
-                  size_t workspace_bytes, void* hip_stream) {
+// ---------------------------------------------------------------------------
+// the iteration chain
+// ---------------------------------------------------------------------------
+hipError_t take_event(dm_ctx* c, hipEvent_t* e) {
+  if (!c->event_pool.empty()) {
+    *e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+dm_status phase_begin(dm_ctx* c, int phase, int* idx) {
+  *idx = -1;
+  if (!c->timing()) return DM_OK;
+  dm_ctx::Mark m{phase, nullptr, nullptr};
+  DM_HIP(c, take_event(c, &m.a));
+  DM_HIP(c, take_event(c, &m.b));
+  DM_HIP(c, hipEventRecord(m.a, c->stream));
+  c->marks.push_back(m);
+  *idx = (int)c->marks.size() - 1;
+  return DM_OK;
+}
+
+dm_status phase_end(dm_ctx* c, int idx) {
+  if (idx < 0) return DM_OK;
+  DM_HIP(c, hipEventRecord(c->marks[idx].b, c->stream));
+  return DM_OK;
+}
+
+template <int F>
+dm_status launch_views_fused(dm_ctx* c) {
+  hipLaunchKernelGGL(dmk::k_fourier_fused<F>, dim3(c->total_views), dim3(F * F / 16), 0,
+                     c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M);
+  DM_LAUNCHED(c, "k_fourier_fused");
+  return DM_OK;
+}
+
+template <int F>
+dm_status launch_views_multipass(dm_ctx* c) {
+  constexpr int B = F / 16, RB = dmk::RowCfg<F>::RB, NT = dmk::RowCfg<F>::NT;
+  const int M = c->M;
+  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views * M, F / RB), dim3(NT), 0,
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  DM_LAUNCHED(c, "k_rows_fwd");
+  const int cb = cols_per_block(F, M);
+  const size_t lds = (size_t)cb * M * (F + 1) * sizeof(float2);
+  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views, F / cb), dim3(cb * B * M), lds,
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M, cb);
+  DM_LAUNCHED(c, "k_cols");
+  hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,
+                     c->scan_dev(), c->vmap(), c->tw(), M);
+  DM_LAUNCHED(c, "k_rows_inv");
+  return DM_OK;
+}
+
+dm_status launch_views(dm_ctx* c) {
+  if (!c->tune.multipass) {
+    switch (c->F) {
+      case 16: return launch_views_fused<16>(c);
+      case 32: return launch_views_fused<32>(c);
+      case 64: return launch_views_fused<64>(c);
+      case 128: return launch_views_fused<128>(c);
+    }
+  } else {
+    switch (c->F) {
+      case 16: return launch_views_multipass<16>(c);
+      case 32: return launch_views_multipass<32>(c);
+      case 64: return launch_views_multipass<64>(c);
+      case 128: return launch_views_multipass<128>(c);
+      case 256: return launch_views_multipass<256>(c);
+    }
+  }
+  c->err = "unsupported frame size for this transform path";
+  return DM_E_UNSUPPORTED;
+}
+
+dm_status launch_iteration(dm_ctx* c) {
+  const int F = c->F, M = c->M, FF = F * F, nb = n_pblk(F);
+  const int n = (int)c->scans.size();
+  int mk;
+  DM_TRY(phase_begin(c, DM_PHASE_VIEWS, &mk));
+  DM_TRY(launch_views(c));
+  DM_TRY(phase_end(c, mk));
+  DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
+  if (c->tune.obj_tile == 16)
+    hipLaunchKernelGGL(dmk::k_object<16>, dim3(c->total_tiles), dim3(256), 0, c->stream,
+                       c->scan_dev(), c->tmap(), F);
+  else
+    hipLaunchKernelGGL(dmk::k_object<32>, dim3(c->total_tiles), dim3(256), 0, c->stream,
+                       c->scan_dev(), c->tmap(), F);
+  DM_LAUNCHED(c, "k_object");
+  DM_TRY(phase_end(c, mk));
+  DM_TRY(phase_begin(c, DM_PHASE_PROBE_PARTIAL, &mk));
+  hipLaunchKernelGGL(dmk::k_probe_partial, dim3(nb, c->total_chunks), dim3(256), 0, c->stream,
+                     c->scan_dev(), c->cmap(), M, F);
+  DM_LAUNCHED(c, "k_probe_partial");
+  DM_TRY(phase_end(c, mk));
+  DM_TRY(phase_begin(c, DM_PHASE_PROBE_FINAL, &mk));
+  hipLaunchKernelGGL(dmk::k_probe_final, dim3(nb, n), dim3(256), 0, c->stream, c->scan_dev(),
+                     M, FF);
+  DM_LAUNCHED(c, "k_probe_final");
+  DM_TRY(phase_end(c, mk));
+  DM_TRY(phase_begin(c, DM_PHASE_ERRORS, &mk));
+  hipLaunchKernelGGL(dmk::k_errors, dim3(n), dim3(256), 0, c->stream, c->scan_dev(), nb, M,
+                     c->flags_dev());
+  DM_LAUNCHED(c, "k_errors");
+  DM_TRY(phase_end(c, mk));
+  if (c->timing()) c->timed_iters++;
+  return DM_OK;
+}
+
+// One iteration as a replayed graph (captured on first use).
+dm_status graph_iteration(dm_ctx* c) {
+  if (!c->graph_exec) {
+    DM_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    dm_status s = launch_iteration(c);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (s != DM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail_hip(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    DM_HIP(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  }
+  DM_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+  return DM_OK;
+}
+
+// Set-up kernels of one scan: views psi = P0 * O0, mode power, counter.
+dm_status init_scan_state(dm_ctx* c, int s) {
+  auto& S = c->scans[s];
+  const ScanLayout& L = S.L;
+  const size_t M = S.d.n_modes, FF = (size_t)S.d.frame * S.d.frame;
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(s, L.P), S.P0, M * FF * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(s, L.O), S.O0, (size_t)S.d.obj_h * S.d.obj_w * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->sat<int>(s, L.counter),
+                     1, 0);
+  DM_LAUNCHED(c, "k_fill_int");
+  hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes), dim3(256), 0, c->stream,
+                     c->sat<float2>(s, L.psi), c->sat<float2>(s, L.P), c->sat<float2>(s, L.O),
+                     c->sat<int>(s, L.pos), S.d.n_modes, S.d.frame, S.d.obj_w);
+  DM_LAUNCHED(c, "k_init_psi");
+  hipLaunchKernelGGL(dmk::k_mode_power, dim3((FF + 255) / 256), dim3(256), 0, c->stream,
+                     c->sat<float2>(s, L.P), c->sat<float>(s, L.D), S.d.n_modes, (int)FF);
+  DM_LAUNCHED(c, "k_mode_power");
+  return DM_OK;
+}
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const float* const* Is,
+                     const int32_t* const* poss, const void* const* P0s, const void* const* O0s,
+                     void* ws, size_t ws_bytes, void* stream) {
   g_init_error.clear();
   if (!out) { g_init_error = "out is NULL"; return DM_E_ARG; }
   *out = nullptr;
   std::string why;
-  dm_status s = validate_desc(desc, why);
-  if (s != DM_OK) { g_init_error = why; return s; }
-  const dm_desc& d = *desc;
-  if (!I_dev || !pos_host || !probe0_dev || !object0_dev || !workspace_dev) {
+  dm_status st = validate_batch(n_scans, descs, why);
+  if (st != DM_OK) { g_init_error = why; return st; }
+  if (!Is || !poss || !P0s || !O0s || !ws) {
     g_init_error = "a required pointer is NULL";
     return DM_E_ARG;
   }
-  if (!aligned8(I_dev) || !aligned8(probe0_dev) || !aligned8(object0_dev)) {
-    g_init_error = "device buffers must be 8-byte aligned";
-    return DM_E_ARG;
-  }
-  if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) {
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) {
     g_init_error = "workspace must be 256-byte aligned";
     return DM_E_ARG;
   }
-  for (int j = 0; j < d.n_frames; ++j) {
-    const int y = pos_host[2 * j], x = pos_host[2 * j + 1];
-    if (y < 0 || x < 0 || y > d.obj_h - d.frame || x > d.obj_w - d.frame) {
-      char msg[160];
-      snprintf(msg, sizeof msg, "view %d at (y=%d, x=%d) leaves the %dx%d object", j, y, x,
-               d.obj_h, d.obj_w);
-      g_init_error = msg;
-      return DM_E_BOUNDS;
+  if ((descs[0].flags & DM_FLAG_GRAPH) && !stream) {
+    g_init_error = "DM_FLAG_GRAPH needs a non-NULL stream";
+    return DM_E_ARG;
+  }
+  for (int s = 0; s < n_scans; ++s) {
+    const dm_desc& d = descs[s];
+    if (!Is[s] || !poss[s] || !P0s[s] || !O0s[s]) {
+      g_init_error = "scan " + std::to_string(s) + ": a required pointer is NULL";
+      return DM_E_ARG;
+    }
+    if (!aligned8(Is[s]) || !aligned8(P0s[s]) || !aligned8(O0s[s])) {
+      g_init_error = "device buffers must be 8-byte aligned";
+      return DM_E_ARG;
+    }
+    for (int j = 0; j < d.n_frames; ++j) {
+      const int y = poss[s][2 * j], x = poss[s][2 * j + 1];
+      if (y < 0 || x < 0 || y > d.obj_h - d.frame || x > d.obj_w - d.frame) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "scan %d: view %d at (y=%d, x=%d) leaves the %dx%d object", s,
+                 j, y, x, d.obj_h, d.obj_w);
+        g_init_error = msg;
+        return DM_E_BOUNDS;
+      }
     }
   }
-  Layout L = make_layout(d);
-  if (workspace_bytes < L.total) {
+  CtxLayout CL = ctx_layout(n_scans, descs);
+  if (ws_bytes < CL.total) {
     char msg[160];
-    snprintf(msg, sizeof msg, "workspace of %zu bytes, %zu needed", workspace_bytes, L.total);
+    snprintf(msg, sizeof msg, "workspace of %zu bytes, %zu needed", ws_bytes, CL.total);
     g_init_error = msg;
     return DM_E_WORKSPACE;
   }
-
   dm_ctx* c = new (std::nothrow) dm_ctx();
   if (!c) { g_init_error = "out of host memory"; return DM_E_ARG; }
-  c->d = d;
-  c->L = L;
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->ws = reinterpret_cast<char*>(workspace_dev);
-  c->I = I_dev;
-  c->pos_host.assign(pos_host, pos_host + 2 * (size_t)d.n_frames);
-
-  std::vector<int> ptr, views;
-  build_tile_lists(d, L, pos_host, ptr, views);
-  if ((int)views.size() > L.nnz_max) {
-    g_init_error = "internal: tile list larger than its bound";
-    delete c;
-    return DM_E_ARG;
+  c->CL = CL;
+  c->F = descs[0].frame;
+  c->M = descs[0].n_modes;
+  c->flags = descs[0].flags;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(ws);
+  std::vector<int2> vmap;
+  for (int s = 0; s < n_scans; ++s) {
+    dm_ctx::Scan S;
+    S.d = descs[s];
+    S.L = CL.sl[s];
+    S.base = CL.scan_base[s];
+    S.I = Is[s];
+    S.P0 = P0s[s];
+    S.O0 = O0s[s];
+    S.pos.assign(poss[s], poss[s] + 2 * (size_t)S.d.n_frames);
+    S.order = spatial_order(S.d, S.pos);
+    for (int j : S.order) vmap.push_back(make_int2(s, j));
+    c->scans.push_back(std::move(S));
   }
-  std::vector<float2> tw = twiddles(d.frame);
-  std::vector<int> order = spatial_order(d, pos_host);
-  const size_t M = d.n_modes, FF = (size_t)d.frame * d.frame;
-
-  auto bail = [&](dm_status st) {
+  c->total_views = (int)vmap.size();
+  auto bail = [&](dm_status e) {
     g_init_error = c->err;
     delete c;
-    return st;
+    return e;
   };
-  dm_status st;
-#define INIT_HIP(call)                                          \
-  do {                                                          \
-    hipError_t e_ = (call);                                     \
-    if (e_ != hipSuccess) return bail(fail_hip(c, e_, #call));  \
+#define INIT_HIP(call)                                         \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return bail(fail_hip(c, e_, #call)); \
   } while (0)
-
-  INIT_HIP(hipMemcpyAsync(c->pos(), pos_host, 2 * sizeof(int) * d.n_frames,
-                          hipMemcpyHostToDevice, c->stream));
-  INIT_HIP(hipMemcpyAsync(c->tile_ptr(), ptr.data(), ptr.size() * sizeof(int),
-                          hipMemcpyHostToDevice, c->stream));
-  INIT_HIP(hipMemcpyAsync(c->tile_views(), views.data(), views.size() * sizeof(int),
-                          hipMemcpyHostToDevice, c->stream));
+  std::vector<float2> tw = twiddles(c->F);
   INIT_HIP(hipMemcpyAsync(c->tw(), tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice,
                           c->stream));
-  INIT_HIP(hipMemcpyAsync(c->order(), order.data(), order.size() * sizeof(int),
+  INIT_HIP(hipMemcpyAsync(c->vmap(), vmap.data(), vmap.size() * sizeof(int2),
                           hipMemcpyHostToDevice, c->stream));
-  INIT_HIP(hipMemcpyAsync(c->P(), probe0_dev, M * FF * 8, hipMemcpyDeviceToDevice, c->stream));
-  INIT_HIP(hipMemcpyAsync(c->O(), object0_dev, (size_t)d.obj_h * d.obj_w * 8,
-                          hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->counter(), 2, 0);
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(), 1, 0);
   INIT_HIP(hipGetLastError());
-  if (!use_fused(d)) {
-    const int lds = (int)((size_t)L.cb * d.n_modes * (d.frame + 1) * sizeof(float2));
-    INIT_HIP(set_cols_lds(d.frame, lds));
+  for (int s = 0; s < n_scans; ++s) {
+    auto& S = c->scans[s];
+    INIT_HIP(hipMemcpyAsync(c->sat<int>(s, S.L.pos), S.pos.data(), S.pos.size() * sizeof(int),
+                            hipMemcpyHostToDevice, c->stream));
+    INIT_HIP(hipMemcpyAsync(c->sat<int>(s, S.L.order), S.order.data(),
+                            S.order.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    const size_t nI = (size_t)S.d.n_frames * S.d.frame * S.d.frame;
+    hipLaunchKernelGGL(dmk::k_check_finite, dim3(1024), dim3(256), 0, c->stream, S.I, nI,
+                       c->flags_dev());
+    INIT_HIP(hipGetLastError());
+    st = init_scan_state(c, s);
+    if (st != DM_OK) return bail(st);
   }
-  const size_t nI = (size_t)d.n_frames * FF;
-  hipLaunchKernelGGL(dmk::k_check_finite, dim3(1024), dim3(256), 0, c->stream, I_dev, nI,
-                     c->flags());
-  INIT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dmk::k_init_psi, dim3(d.n_frames * d.n_modes), dim3(256), 0, c->stream,
-                     c->psi(), c->P(), c->O(), c->pos(), d.n_modes, d.frame, d.obj_w);
-  INIT_HIP(hipGetLastError());
-  st = refresh_mode_power(c);
+  st = apply_tuning(c, default_tuning(descs[0]));  // synchronises
   if (st != DM_OK) return bail(st);
-  int flags_host[2] = {0, 0};
-  INIT_HIP(hipMemcpyAsync(flags_host, c->counter(), sizeof flags_host, hipMemcpyDeviceToHost,
-                          c->stream));
-  INIT_HIP(hipStreamSynchronize(c->stream));
-  if (flags_host[1] & 2) {
+  int flags_host = 0;
+  INIT_HIP(hipMemcpy(&flags_host, c->flags_dev(), sizeof(int), hipMemcpyDeviceToHost));
+  if (flags_host & 2) {
     c->err = "intensities contain NaN or Inf";
     return bail(DM_E_ARG);
   }
@@ -534,53 +710,224 @@ dm_status dm_init(dm_ctx** out, const dm_desc* desc, const float* I_dev, const i
   return DM_OK;
 }
 
+dm_status read_errors(dm_ctx* c, int s, int first, int count, dm_errors* out) {
+  std::vector<DevErrors> tmp(count);
+  DevErrors* ring = c->sat<DevErrors>(s, c->scans[s].L.ring);
+  for (int i = 0; i < count; ++i) {
+    const int slot = (first - 1 + i) % dmk::kRing;
+    DM_HIP(c, hipMemcpyAsync(&tmp[i], ring + slot, sizeof(DevErrors), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  int flags_host = 0;
+  DM_HIP(c, hipMemcpyAsync(&flags_host, c->flags_dev(), sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream));
+  DM_HIP(c, hipStreamSynchronize(c->stream));
+  std::memcpy(out, tmp.data(), sizeof(dm_errors) * count);
+  if (flags_host & 1) {
+    c->err = "a non-finite error norm was produced (the iteration diverged)";
+    return DM_E_NUMERIC;
+  }
+  return DM_OK;
+}
+
+dm_status check_scan(dm_ctx* c, int scan) {
+  dm_status s = check_ctx(c);
+  if (s != DM_OK) return s;
+  if (scan < 0 || scan >= (int)c->scans.size()) {
+    c->err = "scan index out of range";
+    return DM_E_ARG;
+  }
+  return DM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+std::string tune_key(dm_ctx* c) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "gfx";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  int nb = 0;
+  while ((1 << (nb + 1)) <= c->total_views) ++nb;
+  char k[200];
+  snprintf(k, sizeof k, "%s:F%d:M%d:N2^%d:S%zu:flags%u", arch.c_str(), c->F, c->M, nb,
+           c->scans.size(), c->flags & DM_FLAG_MULTIPASS);
+  return k;
+}
+
+bool cache_lookup(const char* path, const std::string& key, dm_tuning* t) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[256];
+    int tile, chunks, multi;
+    if (sscanf(line,
+               "{\"key\": \"%255[^\"]\", \"obj_tile\": %d, \"probe_chunks\": %d, "
+               "\"multipass\": %d",
+               k, &tile, &chunks, &multi) == 4 &&
+        key == k) {
+      t->obj_tile = tile;
+      t->probe_chunks = chunks;
+      t->multipass = multi;
+      t->reserved = 0;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const dm_tuning& t, double ms) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f,
+          "{\"key\": \"%s\", \"obj_tile\": %d, \"probe_chunks\": %d, \"multipass\": %d, "
+          "\"ms_per_iter\": %.6f}\n",
+          key.c_str(), t.obj_tile, t.probe_chunks, t.multipass, ms);
+  fclose(f);
+}
+
+dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
+  if (t.obj_tile != 16 && t.obj_tile != 32) {
+    c->err = "obj_tile must be 16 or 32";
+    return DM_E_ARG;
+  }
+  if (t.probe_chunks < 1 || t.probe_chunks > DM_MAX_PROBE_CHUNKS) {
+    c->err = "probe_chunks out of range";
+    return DM_E_ARG;
+  }
+  if (t.reserved != 0 || (t.multipass != 0 && t.multipass != 1)) {
+    c->err = "bad tuning fields";
+    return DM_E_ARG;
+  }
+  const bool have_spec = c->scans[0].L.tspec != 0;
+  if (t.multipass && !have_spec) {
+    c->err = "the three-kernel path needs DM_FLAG_MULTIPASS at init";
+    return DM_E_ARG;
+  }
+  if (!t.multipass && c->F > 128) {
+    c->err = "F = 256 only has the three-kernel path";
+    return DM_E_ARG;
+  }
+  return DM_OK;
+}
+
+// Median per-iteration time (ms) of `reps` iterations with tuning t.
+dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
+  DM_TRY(apply_tuning(c, t));
+  const uint32_t saved_flags = c->flags;
+  c->flags &= ~DM_FLAG_PHASE_TIMING;
+  dm_status s = launch_iteration(c);  // warm-up
+  std::vector<double> v;
+  for (int r = 0; r < reps && s == DM_OK; ++r) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = take_event(c, &a);
+    if (e == hipSuccess) e = take_event(c, &b);
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    if (e != hipSuccess) { s = fail_hip(c, e, "autotune events"); break; }
+    s = launch_iteration(c);
+    if (s != DM_OK) break;
+    e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float x = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&x, a, b);
+    if (e != hipSuccess) { s = fail_hip(c, e, "autotune timing"); break; }
+    v.push_back(x);
+    c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
+  }
+  c->flags = saved_flags;
+  if (s != DM_OK) return s;
+  std::sort(v.begin(), v.end());
+  *ms = v[v.size() / 2];
+  return DM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t dm_workspace_bytes(const dm_desc* desc) { return dm_batch_workspace_bytes(1, desc); }
+
+size_t dm_batch_workspace_bytes(int32_t n_scans, const dm_desc* descs) {
+  std::string why;
+  if (validate_batch(n_scans, descs, why) != DM_OK) return 0;
+  return ctx_layout(n_scans, descs).total;
+}
+
+dm_status dm_init(dm_ctx** out, const dm_desc* desc, const float* I_dev, const int32_t* pos_host,
+                  const void* probe0_dev, const void* object0_dev, void* workspace_dev,
+                  size_t workspace_bytes, void* hip_stream) {
+  const float* Is[1] = {I_dev};
+  const int32_t* ps[1] = {pos_host};
+  const void* P0s[1] = {probe0_dev};
+  const void* O0s[1] = {object0_dev};
+  return batch_init(out, 1, desc, Is, ps, P0s, O0s, workspace_dev, workspace_bytes, hip_stream);
+}
+
+dm_status dm_batch_init(dm_ctx** out, int32_t n_scans, const dm_desc* descs,
+                        const float* const* I_devs, const int32_t* const* pos_hosts,
+                        const void* const* probe0_devs, const void* const* object0_devs,
+                        void* workspace_dev, size_t workspace_bytes, void* hip_stream) {
+  return batch_init(out, n_scans, descs, I_devs, pos_hosts, probe0_devs, object0_devs,
+                    workspace_dev, workspace_bytes, hip_stream);
+}
+
 dm_status dm_iterate(dm_ctx* c, int32_t n_iter) {
   dm_status s = check_ctx(c);
   if (s != DM_OK) return s;
   if (n_iter < 0) { c->err = "n_iter < 0"; return DM_E_ARG; }
   for (int i = 0; i < n_iter; ++i) {
-    s = launch_iteration(c);
+    s = (c->flags & DM_FLAG_GRAPH) ? graph_iteration(c) : launch_iteration(c);
     if (s != DM_OK) return s;
     c->iters++;
   }
   return DM_OK;
 }
 
-dm_status dm_get_object(dm_ctx* c, void* dst) {
-  dm_status s = check_ctx(c);
+dm_status dm_scan_get_object(dm_ctx* c, int32_t scan, void* dst) {
+  dm_status s = check_scan(c, scan);
   if (s != DM_OK) return s;
   if (!dst) { c->err = "dst is NULL"; return DM_E_ARG; }
-  DM_HIP(c, hipMemcpyAsync(dst, c->O(), (size_t)c->d.obj_h * c->d.obj_w * 8,
+  const auto& S = c->scans[scan];
+  DM_HIP(c, hipMemcpyAsync(dst, c->sat<float2>(scan, S.L.O), (size_t)S.d.obj_h * S.d.obj_w * 8,
                            hipMemcpyDeviceToDevice, c->stream));
   return DM_OK;
 }
 
-dm_status dm_get_probe(dm_ctx* c, void* dst) {
-  dm_status s = check_ctx(c);
+dm_status dm_scan_get_probe(dm_ctx* c, int32_t scan, void* dst) {
+  dm_status s = check_scan(c, scan);
   if (s != DM_OK) return s;
   if (!dst) { c->err = "dst is NULL"; return DM_E_ARG; }
-  DM_HIP(c, hipMemcpyAsync(dst, c->P(), (size_t)c->d.n_modes * c->d.frame * c->d.frame * 8,
+  const auto& S = c->scans[scan];
+  DM_HIP(c, hipMemcpyAsync(dst, c->sat<float2>(scan, S.L.P),
+                           (size_t)S.d.n_modes * S.d.frame * S.d.frame * 8,
                            hipMemcpyDeviceToDevice, c->stream));
   return DM_OK;
 }
 
-static dm_status read_errors(dm_ctx* c, int first, int count, dm_errors* out) {
-  std::vector<DevErrors> tmp(count);
-  int flags_host[2];
-  for (int i = 0; i < count; ++i) {
-    const int slot = (first - 1 + i) % dmk::kRing;
-    DM_HIP(c, hipMemcpyAsync(&tmp[i], c->ring() + slot, sizeof(DevErrors),
-                             hipMemcpyDeviceToHost, c->stream));
+dm_status dm_get_object(dm_ctx* c, void* dst) { return dm_scan_get_object(c, 0, dst); }
+dm_status dm_get_probe(dm_ctx* c, void* dst) { return dm_scan_get_probe(c, 0, dst); }
+
+dm_status dm_scan_error_history(dm_ctx* c, int32_t scan, int32_t first, int32_t count,
+                                dm_errors* out) {
+  dm_status s = check_scan(c, scan);
+  if (s != DM_OK) return s;
+  if (!out || count < 0) { c->err = "bad arguments"; return DM_E_ARG; }
+  if (count == 0) return DM_OK;
+  if (first < 1 || first + count - 1 > c->iters || c->iters - first + 1 > dmk::kRing) {
+    c->err = "requested iterations are not in the error ring";
+    return DM_E_ARG;
   }
-  DM_HIP(c, hipMemcpyAsync(flags_host, c->counter(), sizeof flags_host, hipMemcpyDeviceToHost,
-                           c->stream));
-  DM_HIP(c, hipStreamSynchronize(c->stream));
-  std::memcpy(out, tmp.data(), sizeof(dm_errors) * count);
-  if (flags_host[1] & 1) {
-    c->err = "a non-finite error norm was produced (the iteration diverged)";
-    return DM_E_NUMERIC;
-  }
-  return DM_OK;
+  return read_errors(c, scan, first, count, out);
 }
 
 dm_status dm_error(dm_ctx* c, dm_errors* out) {
@@ -591,38 +938,37 @@ dm_status dm_error(dm_ctx* c, dm_errors* out) {
     std::memset(out, 0, sizeof *out);
     return DM_OK;
   }
-  return read_errors(c, c->iters, 1, out);
+  return read_errors(c, 0, c->iters, 1, out);
 }
 
 dm_status dm_error_history(dm_ctx* c, int32_t first, int32_t count, dm_errors* out) {
-  dm_status s = check_ctx(c);
-  if (s != DM_OK) return s;
-  if (!out || count < 0) { c->err = "bad arguments"; return DM_E_ARG; }
-  if (count == 0) return DM_OK;
-  if (first < 1 || first + count - 1 > c->iters || c->iters - first + 1 > dmk::kRing) {
-    c->err = "requested iterations are not in the error ring";
-    return DM_E_ARG;
-  }
-  return read_errors(c, first, count, out);
+  return dm_scan_error_history(c, 0, first, count, out);
 }
 
 int32_t dm_iterations(const dm_ctx* c) { return c ? c->iters : -1; }
+int32_t dm_n_scans(const dm_ctx* c) { return c ? (int32_t)c->scans.size() : -1; }
 
 dm_status dm_get_state(dm_ctx* c, void* psi_dst, void* probe_dst, void* object_dst,
                        int32_t* iter_host) {
   dm_status s = check_ctx(c);
   if (s != DM_OK) return s;
-  const dm_desc& d = c->d;
-  const size_t FF = (size_t)d.frame * d.frame;
+  if (c->scans.size() != 1) {
+    c->err = "dm_get_state needs a batch of one";
+    return DM_E_STATE;
+  }
+  const auto& S = c->scans[0];
+  const size_t FF = (size_t)S.d.frame * S.d.frame;
   if (psi_dst)
-    DM_HIP(c, hipMemcpyAsync(psi_dst, c->psi(), (size_t)d.n_frames * d.n_modes * FF * 8,
+    DM_HIP(c, hipMemcpyAsync(psi_dst, c->sat<float2>(0, S.L.psi),
+                             (size_t)S.d.n_frames * S.d.n_modes * FF * 8,
                              hipMemcpyDeviceToDevice, c->stream));
   if (probe_dst)
-    DM_HIP(c, hipMemcpyAsync(probe_dst, c->P(), (size_t)d.n_modes * FF * 8,
+    DM_HIP(c, hipMemcpyAsync(probe_dst, c->sat<float2>(0, S.L.P), (size_t)S.d.n_modes * FF * 8,
                              hipMemcpyDeviceToDevice, c->stream));
   if (object_dst)
-    DM_HIP(c, hipMemcpyAsync(object_dst, c->O(), (size_t)d.obj_h * d.obj_w * 8,
-                             hipMemcpyDeviceToDevice, c->stream));
+    DM_HIP(c, hipMemcpyAsync(object_dst, c->sat<float2>(0, S.L.O),
+                             (size_t)S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
+                             c->stream));
   DM_HIP(c, hipStreamSynchronize(c->stream));
   if (iter_host) *iter_host = c->iters;
   return DM_OK;
@@ -632,21 +978,29 @@ dm_status dm_set_state(dm_ctx* c, const void* psi_src, const void* probe_src,
                        const void* object_src, int32_t iter) {
   dm_status s = check_ctx(c);
   if (s != DM_OK) return s;
+  if (c->scans.size() != 1) {
+    c->err = "dm_set_state needs a batch of one";
+    return DM_E_STATE;
+  }
   if (!psi_src || !probe_src || !object_src || iter < 0) {
     c->err = "dm_set_state needs psi, probe, object and iter >= 0";
     return DM_E_ARG;
   }
-  const dm_desc& d = c->d;
-  const size_t FF = (size_t)d.frame * d.frame;
-  DM_HIP(c, hipMemcpyAsync(c->psi(), psi_src, (size_t)d.n_frames * d.n_modes * FF * 8,
+  const auto& S = c->scans[0];
+  const size_t FF = (size_t)S.d.frame * S.d.frame;
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.psi), psi_src,
+                           (size_t)S.d.n_frames * S.d.n_modes * FF * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.P), probe_src, (size_t)S.d.n_modes * FF * 8,
                            hipMemcpyDeviceToDevice, c->stream));
-  DM_HIP(c, hipMemcpyAsync(c->P(), probe_src, (size_t)d.n_modes * FF * 8,
-                           hipMemcpyDeviceToDevice, c->stream));
-  DM_HIP(c, hipMemcpyAsync(c->O(), object_src, (size_t)d.obj_h * d.obj_w * 8,
-                           hipMemcpyDeviceToDevice, c->stream));
-  s = refresh_mode_power(c);
-  if (s != DM_OK) return s;
-  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->counter(), 1, iter);
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.O), object_src,
+                           (size_t)S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
+  hipLaunchKernelGGL(dmk::k_mode_power, dim3((FF + 255) / 256), dim3(256), 0, c->stream,
+                     c->sat<float2>(0, S.L.P), c->sat<float>(0, S.L.D), S.d.n_modes, (int)FF);
+  DM_LAUNCHED(c, "k_mode_power");
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream,
+                     c->sat<int>(0, S.L.counter), 1, iter);
   DM_LAUNCHED(c, "k_fill_int");
   c->iters = iter;
   return DM_OK;
@@ -673,6 +1027,75 @@ dm_status dm_phase_times(dm_ctx* c, double* ms_host, int32_t* n_iter_host) {
   for (int i = 0; i < DM_N_PHASES; ++i) ms_host[i] = acc[i];
   if (n_iter_host) *n_iter_host = c->timed_iters;
   c->timed_iters = 0;
+  return DM_OK;
+}
+
+dm_status dm_get_tuning(const dm_ctx* c, dm_tuning* out) {
+  if (!c || !out) return DM_E_ARG;
+  *out = c->tune;
+  return DM_OK;
+}
+
+dm_status dm_set_tuning(dm_ctx* c, const dm_tuning* t) {
+  dm_status s = check_ctx(c);
+  if (s != DM_OK) return s;
+  if (!t) { c->err = "tuning is NULL"; return DM_E_ARG; }
+  DM_TRY(valid_tuning(c, *t));
+  return apply_tuning(c, *t);
+}
+
+dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning* out) {
+  dm_status s = check_ctx(c);
+  if (s != DM_OK) return s;
+  if (reps < 1) { c->err = "reps must be >= 1"; return DM_E_ARG; }
+  const std::string key = tune_key(c);
+  dm_tuning best = c->tune;
+  if (cache_path && cache_lookup(cache_path, key, &best) && valid_tuning(c, best) == DM_OK) {
+    DM_TRY(apply_tuning(c, best));
+    if (out) *out = best;
+    return DM_OK;
+  }
+  const dm_tuning base = default_tuning(c->scans[0].d);
+  std::vector<dm_tuning> cand;
+  const int chunk_opts[3] = {std::max(1, base.probe_chunks / 2), base.probe_chunks,
+                             std::min(DM_MAX_PROBE_CHUNKS, base.probe_chunks * 2)};
+  const bool have_spec = c->scans[0].L.tspec != 0;
+  for (int mp = 0; mp <= 1; ++mp) {
+    if (mp == 1 && !have_spec) continue;
+    if (mp == 0 && c->F > 128) continue;
+    for (int tile : {16, 32})
+      for (int ch : chunk_opts) {
+        dm_tuning t{tile, ch, mp, 0};
+        bool dup = false;
+        for (auto& u : cand)
+          if (u.obj_tile == t.obj_tile && u.probe_chunks == t.probe_chunks &&
+              u.multipass == t.multipass)
+            dup = true;
+        if (!dup) cand.push_back(t);
+      }
+  }
+  double best_ms = 1e30;
+  for (const auto& t : cand) {
+    double ms = 0;
+    DM_TRY(time_tuning(c, t, reps, &ms));
+    // strictly faster wins; within 0.1% the smaller tile wins
+    if (ms < best_ms * 0.999 || (ms <= best_ms * 1.001 && t.obj_tile < best.obj_tile)) {
+      best_ms = std::min(ms, best_ms);
+      best = t;
+    }
+  }
+  DM_TRY(apply_tuning(c, best));
+  // rebuild the initial state and forget the timed iterations
+  for (int sidx = 0; sidx < (int)c->scans.size(); ++sidx) DM_TRY(init_scan_state(c, sidx));
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(), 1, 0);
+  DM_LAUNCHED(c, "k_fill_int");
+  DM_HIP(c, hipStreamSynchronize(c->stream));
+  c->iters = 0;
+  for (auto& m : c->marks) { c->event_pool.push_back(m.a); c->event_pool.push_back(m.b); }
+  c->marks.clear();
+  c->timed_iters = 0;
+  if (cache_path) cache_store(cache_path, key, best, best_ms);
+  if (out) *out = best;
   return DM_OK;
 }
 

@@ -22,6 +22,33 @@ struct DevErrors {
 
 constexpr int kRing = 4096;
 
+// Device-side description of one scan of a batch: its buffers in the
+// workspace and its sizes.  Kernels look a scan up once per workgroup.
+struct ScanDev {
+  float2* psi;            // [N][M][F][F]
+  const float* I;         // [N][F][F] (caller's)
+  float2* P;              // [M][F][F]
+  float2* O;              // [H][W]
+  const int* pos;         // [N][2]
+  const int* order;       // [N] views in spatial order
+  float2* opart;          // [N][F][F] per-view object numerators
+  float* gscr;            // [N][F][F] per-view modulus scale (fused path)
+  float2* tspec;          // [N][M][F][F] spectrum buffer (three-kernel path)
+  float* D;               // [F][F] mode power
+  float2* num_part;       // [Cmax][M][F][F]
+  float* den_part;        // [Cmax][F][F]
+  float* err_psi;         // [n_psi_parts][2]
+  float* err_obj;         // [ntiles_max][2]
+  float* err_probe;       // [n_pblk][M][2]
+  const int* tile_ptr;    // [ntiles + 1]
+  const int* tile_views;  // [nnz]
+  int* counter;           // iteration counter of this scan
+  DevErrors* ring;        // [kRing]
+  int N, H, W, tiles_x, ntiles, C, chunk, n_psi_parts;
+  float beta;
+  int pad;
+};
+
 // ---------------------------------------------------------------------------
 // block reduction of two floats (fixed order: lanes, then waves in order)
 // ---------------------------------------------------------------------------
@@ -209,10 +236,8 @@ __device__ __forceinline__ int xcd_slot(int b, int nblocks) {
 
 template <int F>
 __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
-    float2* __restrict__ psi, const float* __restrict__ I, const float2* __restrict__ P,
-    const float2* __restrict__ O, const int* __restrict__ pos, const int* __restrict__ order,
-    const float2* __restrict__ tw, float2* __restrict__ opart, float* __restrict__ gscr,
-    float* __restrict__ err_psi, int N, int M, int H, int W, float beta) {
+    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
+    const float2* __restrict__ tw, int M) {
   constexpr int B = F / 16;
   constexpr int NT = F * B;
   constexpr int LD = F + 1;
@@ -221,7 +246,19 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
   __shared__ float red[2 * ((NT + 63) / 64)];
 
   const int t = threadIdx.x;
-  const int j = order[xcd_slot(blockIdx.x, N)];
+  const int2 vm = vmap[xcd_slot(blockIdx.x, total)];
+  const ScanDev& sc = scans[vm.x];
+  const int j = vm.y;
+  float2* __restrict__ psi = sc.psi;
+  const float* __restrict__ I = sc.I;
+  const float2* __restrict__ P = sc.P;
+  const float2* __restrict__ O = sc.O;
+  const int* __restrict__ pos = sc.pos;
+  float2* __restrict__ opart = sc.opart;
+  float* __restrict__ gscr = sc.gscr;
+  float* __restrict__ err_psi = sc.err_psi;
+  const int H = sc.H, W = sc.W;
+  const float beta = sc.beta;
   const int c = t % F;
   const int g = wave_uniform_div<F>(t);
   const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
@@ -238,9 +275,14 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 
   // F = 128 runs 1024 threads with at most 128 VGPRs each: the view is read
   // again in the epilogue instead of being held through both transforms.
+  // Smaller frames hold it.  Either way the next mode's view is prefetched
+  // into registers while the current mode's transforms run.
   constexpr bool kHold = (F < 128);
   float2 a[16];
+  float2 pf[16];    // prefetched view of the next mode to be transformed
   float2 hold[kHold ? 16 : 1];
+#pragma unroll
+  for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, u1 * B * F * 8);
   {
     float S[16];
 #pragma unroll
@@ -252,12 +294,16 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 #pragma unroll
       for (int u1 = 0; u1 < 16; ++u1) {
         const int srow = u1 * B * F * 8;
-        const float2 ps = bload2(rpsi, vF, sm + srow);
         const float2 phi = cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-        if constexpr (kHold) hold[u1] = ps;
+        a[u1] = make_float2(2.f * phi.x - pf[u1].x, 2.f * phi.y - pf[u1].y);
         if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
+      if (m + 1 < M) {
+        // next mode's view: in flight during this mode's transform
+#pragma unroll
+        for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, sm + FF * 8 + u1 * B * F * 8);
+      }
+      // (after the last mode, pf keeps that mode's view for pass 2)
       Frame2D<F, -1>::fwd(a, buf, tw, c, g);
 #pragma unroll
       for (int r = 0; r < 16; ++r) S[r] += cabs2(a[r]);
@@ -293,19 +339,27 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 
   for (int m = M - 1; m >= 0; --m) {
     const int sm = m * FF * 8;
+    // pf holds this mode's view (from pass 1 for m = M-1, prefetched below
+    // otherwise)
+    if constexpr (kHold) {
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) hold[u1] = pf[u1];
+    }
     if (m != M - 1) {
 #pragma unroll
       for (int u1 = 0; u1 < 16; ++u1) {
         const int srow = u1 * B * F * 8;
-        const float2 ps = bload2(rpsi, vF, sm + srow);
         const float2 phi =
             cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-        if constexpr (kHold) hold[u1] = ps;
+        a[u1] = make_float2(2.f * phi.x - pf[u1].x, 2.f * phi.y - pf[u1].y);
         if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
-      Frame2D<F, -1>::fwd(a, buf, tw, c, g);
     }
+    if (m > 0) {
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, sm - FF * 8 + u1 * B * F * 8);
+    }
+    if (m != M - 1) Frame2D<F, -1>::fwd(a, buf, tw, c, g);
 #pragma unroll
     for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], bload1(rg, vG, r * NT * 4));
     Frame2D<F, 1>::inv(a, buf, tw, c, g);
@@ -351,14 +405,21 @@ struct RowCfg {
 // (1) Z = 2 P O - psi and the DFT along rows, RB rows per block.
 template <int F>
 __global__ __launch_bounds__(256) void k_rows_fwd(
-    const float2* __restrict__ psi, const float2* __restrict__ P, const float2* __restrict__ O,
-    const int* __restrict__ pos, const float2* __restrict__ tw, float2* __restrict__ T,
-    int M, int W) {
+    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
+    const float2* __restrict__ tw, int M) {
   constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
   __shared__ float2 buf[RB * LD];
   const int t = threadIdx.x;
-  const int jm = blockIdx.x;
-  const int j = jm / M, m = jm % M;
+  const int2 vm = vmap[blockIdx.x / M];
+  const ScanDev& sc = scans[vm.x];
+  const int j = vm.y, m = blockIdx.x % M;
+  const int jm = j * M + m;
+  const float2* __restrict__ psi = sc.psi;
+  const float2* __restrict__ P = sc.P;
+  const float2* __restrict__ O = sc.O;
+  const int* __restrict__ pos = sc.pos;
+  float2* __restrict__ T = sc.tspec;
+  const int W = sc.W;
   const int rl = t / B, n2 = t % B;
   const int row = blockIdx.y * RB + rl;
   const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
@@ -398,12 +459,17 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 // sum, the modulus scale, and the inverse DFT along columns, in place in T.
 // Block = CB * B * M threads; dynamic LDS = CB * M * (F + 1) float2.
 template <int F>
-__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ T, const float* __restrict__ I,
+__global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans,
+                                               const int2* __restrict__ vmap,
                                                const float2* __restrict__ tw, int M, int CB) {
   constexpr int B = F / 16, LD = F + 1, FF = F * F, NI = 16 / B;
   extern __shared__ float2 dyn[];
   const int t = threadIdx.x;
-  const int j = blockIdx.x;
+  const int2 vm = vmap[blockIdx.x];
+  const ScanDev& sc = scans[vm.x];
+  const int j = vm.y;
+  float2* __restrict__ T = sc.tspec;
+  const float* __restrict__ I = sc.I;
   const int col0 = blockIdx.y * CB;
   const int c = t % CB;
   const int rest = t / CB;
@@ -474,15 +540,25 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ T, const flo
 // of the view and eps_psi partial sums; all modes of RB rows per block.
 template <int F>
 __global__ __launch_bounds__(256) void k_rows_inv(
-    float2* __restrict__ psi, const float2* __restrict__ P, const float2* __restrict__ O,
-    const int* __restrict__ pos, const float2* __restrict__ tw, const float2* __restrict__ T,
-    float2* __restrict__ opart, float* __restrict__ err_psi, int M, int W, float beta) {
+    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
+    const float2* __restrict__ tw, int M) {
   constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
   constexpr int NT = RowCfg<F>::NT;
   __shared__ float2 buf[RB * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
   const int t = threadIdx.x;
-  const int j = blockIdx.x;
+  const int2 vm = vmap[blockIdx.x];
+  const ScanDev& sc = scans[vm.x];
+  const int j = vm.y;
+  float2* __restrict__ psi = sc.psi;
+  const float2* __restrict__ P = sc.P;
+  const float2* __restrict__ O = sc.O;
+  const int* __restrict__ pos = sc.pos;
+  const float2* __restrict__ T = sc.tspec;
+  float2* __restrict__ opart = sc.opart;
+  float* __restrict__ err_psi = sc.err_psi;
+  const int W = sc.W;
+  const float beta = sc.beta;
   const int rl = t / B, n2 = t % B;
   const int row = blockIdx.y * RB + rl;
   const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
@@ -549,16 +625,23 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 // still adds them in ascending order.
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(256) void k_object(
-    const float2* __restrict__ opart, const float* __restrict__ D, float2* __restrict__ O,
-    const int* __restrict__ pos, const int* __restrict__ tile_ptr,
-    const int* __restrict__ tile_views, int F, int H, int W, int tiles_x,
-    float* __restrict__ err_obj) {
+__global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scans,
+                                                const int2* __restrict__ tmap, int F) {
   constexpr int PPT = T * T / 256;  // pixels per thread
   constexpr int RSTEP = 256 / T;    // rows between a thread's pixels
   __shared__ float red[8];
   const int t = threadIdx.x;
-  const int tile = blockIdx.x;
+  const int2 tm = tmap[blockIdx.x];
+  const ScanDev& sc = scans[tm.x];
+  const int tile = tm.y;
+  const float2* __restrict__ opart = sc.opart;
+  const float* __restrict__ D = sc.D;
+  float2* __restrict__ O = sc.O;
+  const int* __restrict__ pos = sc.pos;
+  const int* __restrict__ tile_ptr = sc.tile_ptr;
+  const int* __restrict__ tile_views = sc.tile_views;
+  float* __restrict__ err_obj = sc.err_obj;
+  const int H = sc.H, W = sc.W, tiles_x = sc.tiles_x;
   const int ty = tile / tiles_x, tx = tile % tiles_x;
   const int col = t % T, row0 = t / T;
   const int cx = tx * T + col;
@@ -633,13 +716,21 @@ __global__ __launch_bounds__(256) void k_object(
 // sum_j conj(O'[win_j]) psi'_{j,k} for every mode and sum_j |O'[win_j]|^2.
 // Modes in groups of 8 held in registers; two views' loads in flight.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_probe_partial(
-    const float2* __restrict__ psi, const float2* __restrict__ O, const int* __restrict__ pos,
-    const int* __restrict__ order, int N, int M, int F, int W, int chunk,
-    float2* __restrict__ num_part, float* __restrict__ den_part) {
+__global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict__ scans,
+                                                       const int2* __restrict__ cmap, int M,
+                                                       int F) {
   const int FF = F * F;
   const int pix = blockIdx.x * 256 + threadIdx.x;
-  const int cidx = blockIdx.y;
+  const int2 cm = cmap[blockIdx.y];
+  const ScanDev& sc = scans[cm.x];
+  const int cidx = cm.y;
+  const float2* __restrict__ psi = sc.psi;
+  const float2* __restrict__ O = sc.O;
+  const int* __restrict__ pos = sc.pos;
+  const int* __restrict__ order = sc.order;
+  float2* __restrict__ num_part = sc.num_part;
+  float* __restrict__ den_part = sc.den_part;
+  const int N = sc.N, W = sc.W, chunk = sc.chunk;
   const int j0 = cidx * chunk;
   const int j1 = min(N, j0 + chunk);
   const int u = pix / F, v = pix % F;
@@ -688,11 +779,16 @@ __global__ __launch_bounds__(256) void k_probe_partial(
 // Probe update, stage 2: fixed-order sum over chunks, division (zero
 // denominators keep the old value), per-mode eps_P partials and the mode
 // power D = sum_k |P'_k|^2 used by the next object update.
-__global__ __launch_bounds__(256) void k_probe_final(
-    const float2* __restrict__ num_part, const float* __restrict__ den_part,
-    float2* __restrict__ P, float* __restrict__ D, int C, int M, int FF,
-    float* __restrict__ err_probe) {
+__global__ __launch_bounds__(256) void k_probe_final(const ScanDev* __restrict__ scans, int M,
+                                                     int FF) {
   __shared__ float red[8];
+  const ScanDev& sc = scans[blockIdx.y];
+  const float2* __restrict__ num_part = sc.num_part;
+  const float* __restrict__ den_part = sc.den_part;
+  float2* __restrict__ P = sc.P;
+  float* __restrict__ D = sc.D;
+  float* __restrict__ err_probe = sc.err_probe;
+  const int C = sc.C;
   const int pix = blockIdx.x * 256 + threadIdx.x;
   float den = 0.f;
   for (int cc = 0; cc < C; ++cc) den += den_part[(size_t)cc * FF + pix];
@@ -735,11 +831,16 @@ __device__ double block_sum_d(double x, double* red) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_errors(
-    const float* __restrict__ err_psi, int n_psi, const float* __restrict__ err_obj, int n_obj,
-    const float* __restrict__ err_probe, int n_pblk, int M, int* __restrict__ counter,
-    DevErrors* __restrict__ ring, int* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scans, int n_pblk,
+                                                int M, int* __restrict__ flags) {
   __shared__ double red[256];
+  const ScanDev& sc = scans[blockIdx.x];
+  const float* __restrict__ err_psi = sc.err_psi;
+  const float* __restrict__ err_obj = sc.err_obj;
+  const float* __restrict__ err_probe = sc.err_probe;
+  int* __restrict__ counter = sc.counter;
+  DevErrors* __restrict__ ring = sc.ring;
+  const int n_psi = sc.n_psi_parts, n_obj = sc.ntiles;
   const int t = threadIdx.x;
   double v[4];
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -777,7 +878,7 @@ __global__ __launch_bounds__(256) void k_errors(
     }
     ring[it % kRing] = e;
     *counter = it + 1;
-    if (bad) *flags |= 1;
+    if (bad) atomicOr(flags, 1);
   }
 }
 

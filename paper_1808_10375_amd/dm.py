@@ -29,13 +29,18 @@ DM_FP32_FFT = 0
 DM_BF16X3_DFT = 1
 DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 256)
 DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
+DM_FLAG_GRAPH = 4         # capture one iteration into a hipGraph and replay it
 DM_MAX_MODES = 16
+DM_MAX_PROBE_CHUNKS = 64
 PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]
 
 EXPORTED = [
     "dm_workspace_bytes", "dm_init", "dm_iterate", "dm_get_object", "dm_get_probe",
     "dm_error", "dm_error_history", "dm_iterations", "dm_get_state", "dm_set_state",
     "dm_free", "dm_status_str", "dm_last_error", "dm_phase_times",
+    "dm_batch_workspace_bytes", "dm_batch_init", "dm_n_scans", "dm_scan_get_object",
+    "dm_scan_get_probe", "dm_scan_error_history", "dm_get_tuning", "dm_set_tuning",
+    "dm_autotune",
 ]
 
 
@@ -55,6 +60,15 @@ class dm_errors(ctypes.Structure):
         return {"iter": self.iter, "eps_psi": self.eps_psi, "eps_obj": self.eps_obj,
                 "eps_probe": self.eps_probe,
                 "eps_probe_mode": [self.eps_probe_mode[k] for k in range(n_modes)]}
+
+
+class dm_tuning(ctypes.Structure):
+    _fields_ = [("obj_tile", ctypes.c_int32), ("probe_chunks", ctypes.c_int32),
+                ("multipass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {"obj_tile": self.obj_tile, "probe_chunks": self.probe_chunks,
+                "multipass": self.multipass}
 
 
 class DMError(RuntimeError):
@@ -99,6 +113,26 @@ def lib():
     L.dm_set_state.restype = i32
     L.dm_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     L.dm_phase_times.restype = i32
+    L.dm_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(dm_desc)]
+    L.dm_batch_workspace_bytes.restype = u64
+    L.dm_batch_init.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dm_desc),
+                                ctypes.POINTER(vp), ctypes.POINTER(ctypes.POINTER(i32)),
+                                ctypes.POINTER(vp), ctypes.POINTER(vp), vp, u64, vp]
+    L.dm_batch_init.restype = i32
+    L.dm_n_scans.argtypes = [vp]
+    L.dm_n_scans.restype = i32
+    L.dm_scan_get_object.argtypes = [vp, i32, vp]
+    L.dm_scan_get_object.restype = i32
+    L.dm_scan_get_probe.argtypes = [vp, i32, vp]
+    L.dm_scan_get_probe.restype = i32
+    L.dm_scan_error_history.argtypes = [vp, i32, i32, i32, ctypes.POINTER(dm_errors)]
+    L.dm_scan_error_history.restype = i32
+    L.dm_get_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
+    L.dm_get_tuning.restype = i32
+    L.dm_set_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
+    L.dm_set_tuning.restype = i32
+    L.dm_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(dm_tuning)]
+    L.dm_autotune.restype = i32
     L.dm_free.argtypes = [vp]
     L.dm_free.restype = None
     L.dm_status_str.argtypes = [i32]
@@ -211,6 +245,70 @@ def dm_phase_times(ctx):
     return {p: arr[i] for i, p in enumerate(PHASES)}, int(n.value)
 
 
+def dm_batch_workspace_bytes(descs) -> int:
+    arr = (dm_desc * len(descs))(*descs)
+    return int(lib().dm_batch_workspace_bytes(len(descs), arr))
+
+
+def dm_batch_init(descs, Is, poss, probe0s, object0s, workspace, stream=None):
+    """Context for a batch of scans (same F, M, flags); per-scan lists of
+    torch device tensors and host position arrays."""
+    n = len(descs)
+    arr = (dm_desc * n)(*descs)
+    poss = [np.ascontiguousarray(np.asarray(p, dtype=np.int32)) for p in poss]
+    for d, p in zip(descs, poss):
+        if p.shape != (d.n_frames, 2):
+            raise ValueError("positions must have shape (n_frames, 2)")
+    vp = ctypes.c_void_p
+    I_arr = (vp * n)(*[_ptr(t) for t in Is])
+    P_arr = (vp * n)(*[_ptr(t) for t in probe0s])
+    O_arr = (vp * n)(*[_ptr(t) for t in object0s])
+    pos_arr = (ctypes.POINTER(ctypes.c_int32) * n)(
+        *[p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for p in poss])
+    ctx = ctypes.c_void_p()
+    st = lib().dm_batch_init(ctypes.byref(ctx), n, arr, I_arr, pos_arr, P_arr, O_arr,
+                             _ptr(workspace), int(workspace.numel() * workspace.element_size()),
+                             _stream_handle(stream))
+    _check(st, None)
+    return ctx
+
+
+def dm_n_scans(ctx) -> int:
+    return int(lib().dm_n_scans(ctx))
+
+
+def dm_scan_get_object(ctx, scan: int, dst):
+    _check(lib().dm_scan_get_object(ctx, int(scan), _ptr(dst)), ctx)
+
+
+def dm_scan_get_probe(ctx, scan: int, dst):
+    _check(lib().dm_scan_get_probe(ctx, int(scan), _ptr(dst)), ctx)
+
+
+def dm_scan_error_history(ctx, scan: int, first: int, count: int):
+    arr = (dm_errors * max(count, 1))()
+    _check(lib().dm_scan_error_history(ctx, int(scan), int(first), int(count), arr), ctx)
+    return [arr[i] for i in range(count)]
+
+
+def dm_get_tuning(ctx) -> dm_tuning:
+    t = dm_tuning()
+    _check(lib().dm_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return t
+
+
+def dm_set_tuning(ctx, obj_tile: int, probe_chunks: int, multipass: int = 0):
+    t = dm_tuning(int(obj_tile), int(probe_chunks), int(multipass), 0)
+    _check(lib().dm_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def dm_autotune(ctx, reps: int = 5, cache_path: Optional[str] = None) -> dm_tuning:
+    t = dm_tuning()
+    _check(lib().dm_autotune(ctx, int(reps), cache_path.encode() if cache_path else None,
+                             ctypes.byref(t)), ctx)
+    return t
+
+
 def dm_free(ctx):
     if ctx:
         lib().dm_free(ctx)
@@ -287,6 +385,96 @@ class DMContext:
 
     def phase_times(self):
         return dm_phase_times(self.ctx)
+
+    def tuning(self) -> dict:
+        return dm_get_tuning(self.ctx).to_dict()
+
+    def set_tuning(self, obj_tile, probe_chunks, multipass=0):
+        dm_set_tuning(self.ctx, obj_tile, probe_chunks, multipass)
+
+    def autotune(self, reps=5, cache_path=None) -> dict:
+        return dm_autotune(self.ctx, reps, cache_path).to_dict()
+
+    @property
+    def iterations(self) -> int:
+        return dm_iterations(self.ctx)
+
+    def free(self):
+        if getattr(self, "ctx", None):
+            dm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class DMBatch:
+    """Many scans (same frame size and mode count) advanced together: one
+    launch per phase per iteration for the whole batch."""
+
+    def __init__(self, scans, beta=0.8, flags=0, stream=None, device=None):
+        """scans: list of dicts with numpy or torch arrays I, pos, P0, O0."""
+        import torch
+        self.device = torch.device(device or "cuda:0")
+        self.stream = stream
+        self._keep = []
+        descs, Is, poss, P0s, O0s = [], [], [], [], []
+        for sc in scans:
+            I = torch.as_tensor(sc["I"], dtype=torch.float32).to(self.device).contiguous()
+            P0 = torch.as_tensor(sc["P0"]).to(self.device, torch.complex64).contiguous()
+            O0 = torch.as_tensor(sc["O0"]).to(self.device, torch.complex64).contiguous()
+            n, f, _ = I.shape
+            descs.append(make_desc(n, f, P0.shape[0], O0.shape[0], O0.shape[1],
+                                   sc.get("beta", beta), DM_FP32_FFT, flags))
+            Is.append(I); P0s.append(P0); O0s.append(O0)
+            poss.append(np.asarray(sc["pos"], dtype=np.int32))
+        self.descs = descs
+        nbytes = dm_batch_workspace_bytes(descs)
+        if nbytes == 0:
+            raise DMError(DM_E_ARG, "invalid batch description")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._keep = [Is, P0s, O0s]
+        self.ctx = dm_batch_init(descs, Is, poss, P0s, O0s, self.workspace, stream)
+
+    @property
+    def n_scans(self) -> int:
+        return dm_n_scans(self.ctx)
+
+    def iterate(self, n: int = 1):
+        dm_iterate(self.ctx, n)
+
+    def object(self, scan: int):
+        import torch
+        d = self.descs[scan]
+        out = torch.empty((d.obj_h, d.obj_w), dtype=torch.complex64, device=self.device)
+        dm_scan_get_object(self.ctx, scan, out)
+        return out
+
+    def probe(self, scan: int):
+        import torch
+        d = self.descs[scan]
+        out = torch.empty((d.n_modes, d.frame, d.frame), dtype=torch.complex64,
+                          device=self.device)
+        dm_scan_get_probe(self.ctx, scan, out)
+        return out
+
+    def error_history(self, scan: int, first: int = 1, count: Optional[int] = None):
+        if count is None:
+            count = dm_iterations(self.ctx) - first + 1
+        m = self.descs[scan].n_modes
+        return [e.to_dict(m) for e in dm_scan_error_history(self.ctx, scan, first, count)]
+
+    def tuning(self) -> dict:
+        return dm_get_tuning(self.ctx).to_dict()
+
+    def set_tuning(self, obj_tile, probe_chunks, multipass=0):
+        dm_set_tuning(self.ctx, obj_tile, probe_chunks, multipass)
+
+    def autotune(self, reps=5, cache_path=None) -> dict:
+        return dm_autotune(self.ctx, reps, cache_path).to_dict()
 
     @property
     def iterations(self) -> int:

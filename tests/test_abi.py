@@ -37,6 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(dm.dm_desc) == 32
     assert ctypes.sizeof(dm.dm_errors) == 80
+    assert ctypes.sizeof(dm.dm_tuning) == 16
 
 
 def desc(**kw):
@@ -52,7 +53,7 @@ def test_workspace_bytes_valid_and_invalid():
     assert dm.dm_workspace_bytes(desc(n_frames=20)) > n
     for bad in (dict(frame=48), dict(frame=8), dict(frame=512), dict(n_modes=0),
                 dict(n_modes=17), dict(beta=1.5), dict(beta=-0.1), dict(obj_h=16),
-                dict(n_frames=0), dict(precision=7), dict(flags=4)):
+                dict(n_frames=0), dict(precision=7), dict(flags=8), dict(flags=6)):
         assert dm.dm_workspace_bytes(desc(**bad)) == 0, bad
     # F = 256 needs the multi-pass spectrum buffer as well
     d256 = desc(frame=256, obj_h=300, obj_w=300)
@@ -102,3 +103,42 @@ def test_calls_on_null_context():
     L.dm_free(None)
     for s in range(0, -8, -1):
         assert dm.dm_status_str(s).startswith("DM_")
+
+
+def test_batch_workspace_and_validation():
+    a = desc(n_frames=10)
+    b = desc(n_frames=30, obj_h=120, obj_w=100, beta=0.5)
+    one = dm.dm_batch_workspace_bytes([a])
+    assert one == dm.dm_workspace_bytes(a)
+    two = dm.dm_batch_workspace_bytes([a, b])
+    assert two > one + dm.dm_workspace_bytes(b) // 2
+    # mixed frame sizes or mode counts are rejected
+    assert dm.dm_batch_workspace_bytes([a, desc(frame=64)]) == 0
+    assert dm.dm_batch_workspace_bytes([a, desc(n_modes=3)]) == 0
+    assert dm.dm_batch_workspace_bytes([a, desc(flags=1)]) == 0
+
+
+def test_batch_init_bounds_reported_per_scan():
+    import numpy as np
+    a = desc(n_frames=4)
+    b = desc(n_frames=3)
+    L = dm.lib()
+    arr = (dm.dm_desc * 2)(a, b)
+    pa = np.zeros((4, 2), np.int32)
+    pb = np.zeros((3, 2), np.int32)
+    pb[2] = (0, 90)
+    vp = ctypes.c_void_p
+    ptrs = (vp * 2)(256, 256)
+    pos_arr = (ctypes.POINTER(ctypes.c_int32) * 2)(
+        pa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        pb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    ctx = ctypes.c_void_p()
+    st = L.dm_batch_init(ctypes.byref(ctx), 2, arr, ptrs, pos_arr, ptrs, ptrs, 256,
+                         dm.dm_batch_workspace_bytes([a, b]), None)
+    assert st == dm.DM_E_BOUNDS and "scan 1: view 2" in dm.dm_last_error(None)
+    # graph capture needs a stream
+    g = desc(n_frames=4, flags=dm.DM_FLAG_GRAPH)
+    arr1 = (dm.dm_desc * 1)(g)
+    st = L.dm_batch_init(ctypes.byref(ctx), 1, arr1, ptrs, pos_arr, ptrs, ptrs, 256,
+                         dm.dm_batch_workspace_bytes([g]), None)
+    assert st == dm.DM_E_ARG and "stream" in dm.dm_last_error(None)

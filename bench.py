@@ -113,6 +113,51 @@ def copy_calibration(reps: int = 3):
     print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
+def bench_batched(steps: int, warmup: int, conv_iters: int):
+    """16 scans of uneven size (200-3000 views, 3 modes, 128x128 frames,
+    1024x1024 objects) advanced together: one hipGraph launch per iteration,
+    launch shapes from the autotuner."""
+    import torch
+    from paper_1808_10375_amd import dm, synth
+    t0 = time.time()
+    scans = synth.uneven_spirals_128(1000)
+    print(f"# generated 16 uneven scans in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    sizes = [sc.n_frames for sc in scans]
+    m = scans[0].n_modes
+    with torch.cuda.stream(stream):
+        b = dm.DMBatch([dict(I=sc.I, pos=sc.pos, P0=sc.P0, O0=sc.O0, beta=sc.beta)
+                        for sc in scans], flags=dm.DM_FLAG_GRAPH, stream=stream)
+        tune = b.autotune(reps=3)
+        b.iterate(warmup)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        b.iterate(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        done = warmup + steps
+        if conv_iters > done:
+            b.iterate(conv_iters - done)
+        n_it = max(conv_iters, done)
+        final = [b.error_history(s, n_it, 1)[0]["eps_probe"] for s in range(len(scans))]
+        b.free()
+    total = sum(sizes)
+    return {"workload": "16 scans, %d..%d views each (%d total), 3 modes, 128x128 frames, "
+                        "1024x1024 objects, Poisson 1e5" % (min(sizes), max(sizes), total),
+            "value": total * m / (elapsed / steps), "unit": "frame·mode/s",
+            "ms_per_step": 1e3 * elapsed / steps, "steps": steps, "warmup": warmup,
+            "launch": "one hipGraph per iteration (5 kernels for all 16 scans)",
+            "tuning": tune, "alg_bytes_per_step": step_alg_bytes(total, m, 128),
+            "step_roofline_frac": step_alg_bytes(total, m, 128) / (elapsed / steps) / 1e9
+            / HBM_PEAK_GBS,
+            "err_after_%d" % n_it: {"min": min(final), "median": float(np.median(final)),
+                                    "max": max(final)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +168,8 @@ def main():
                     help="total iterations from the cold start for the err curve")
     ap.add_argument("--cpu-sample", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched-scans (and other forms') measurements")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -220,6 +267,8 @@ def main():
         "iters_to_err_1e-3": reach,
         "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
     }
+    if not args.no_forms and args.config == 1:
+        out["forms"] = {"batched": bench_batched(args.steps, args.warmup, args.conv_iters)}
     if not args.no_cpu:
         print("# timing the FP64 oracle on a sample of the scan", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, min(args.cpu_sample, n))

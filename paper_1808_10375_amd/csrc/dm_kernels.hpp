@@ -244,8 +244,10 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
   constexpr int FF = F * F;
   __shared__ float2 buf[F * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
+  __shared__ float2 twl[F];  // twiddles read from LDS, not held in SGPRs
 
   const int t = threadIdx.x;
+  for (int i = t; i < F; i += NT) twl[i] = tw[i];
   const int2 vm = vmap[xcd_slot(blockIdx.x, total)];
   const ScanDev& sc = scans[vm.x];
   const int j = vm.y;
@@ -275,14 +277,9 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 
   // F = 128 runs 1024 threads with at most 128 VGPRs each: the view is read
   // again in the epilogue instead of being held through both transforms.
-  // Smaller frames hold it.  Either way the next mode's view is prefetched
-  // into registers while the current mode's transforms run.
   constexpr bool kHold = (F < 128);
   float2 a[16];
-  float2 pf[16];    // prefetched view of the next mode to be transformed
   float2 hold[kHold ? 16 : 1];
-#pragma unroll
-  for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, u1 * B * F * 8);
   {
     float S[16];
 #pragma unroll
@@ -294,17 +291,13 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 #pragma unroll
       for (int u1 = 0; u1 < 16; ++u1) {
         const int srow = u1 * B * F * 8;
+        const float2 ps = bload2(rpsi, vF, sm + srow);
         const float2 phi = cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - pf[u1].x, 2.f * phi.y - pf[u1].y);
+        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+        if constexpr (kHold) hold[u1] = ps;
         if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
-      if (m + 1 < M) {
-        // next mode's view: in flight during this mode's transform
-#pragma unroll
-        for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, sm + FF * 8 + u1 * B * F * 8);
-      }
-      // (after the last mode, pf keeps that mode's view for pass 2)
-      Frame2D<F, -1>::fwd(a, buf, tw, c, g);
+      Frame2D<F, -1>::fwd(a, buf, twl, c, g);
 #pragma unroll
       for (int r = 0; r < 16; ++r) S[r] += cabs2(a[r]);
     }
@@ -339,30 +332,22 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
 
   for (int m = M - 1; m >= 0; --m) {
     const int sm = m * FF * 8;
-    // pf holds this mode's view (from pass 1 for m = M-1, prefetched below
-    // otherwise)
-    if constexpr (kHold) {
-#pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) hold[u1] = pf[u1];
-    }
     if (m != M - 1) {
 #pragma unroll
       for (int u1 = 0; u1 < 16; ++u1) {
         const int srow = u1 * B * F * 8;
+        const float2 ps = bload2(rpsi, vF, sm + srow);
         const float2 phi =
             cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - pf[u1].x, 2.f * phi.y - pf[u1].y);
+        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+        if constexpr (kHold) hold[u1] = ps;
         if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
+      Frame2D<F, -1>::fwd(a, buf, twl, c, g);
     }
-    if (m > 0) {
-#pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) pf[u1] = bload2(rpsi, vF, sm - FF * 8 + u1 * B * F * 8);
-    }
-    if (m != M - 1) Frame2D<F, -1>::fwd(a, buf, tw, c, g);
 #pragma unroll
     for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], bload1(rg, vG, r * NT * 4));
-    Frame2D<F, 1>::inv(a, buf, tw, c, g);
+    Frame2D<F, 1>::inv(a, buf, twl, c, g);
 #pragma unroll
     for (int u1 = 0; u1 < 16; ++u1) {
       const int srow = u1 * B * F * 8;

@@ -470,10 +470,17 @@ dm_status phase_end(dm_ctx* c, int idx) {
   return DM_OK;
 }
 
+// Virtual threads per thread of the fused view kernel.  Two at F = 128 (512
+// threads, 256 VGPRs each) pass parity but run 1.4x slower than one (1024
+// threads, 128 VGPRs), so every frame size uses one.
+template <int F>
+constexpr int fused_v() { return 1; }
+
 template <int F>
 dm_status launch_views_fused(dm_ctx* c) {
-  hipLaunchKernelGGL(dmk::k_fourier_fused<F>, dim3(c->total_views), dim3(F * F / 16), 0,
-                     c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M);
+  constexpr int V = fused_v<F>();
+  hipLaunchKernelGGL((dmk::k_fourier_fused<F, V>), dim3(c->total_views), dim3(F * F / (16 * V)),
+                     0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M);
   DM_LAUNCHED(c, "k_fourier_fused");
   return DM_OK;
 }

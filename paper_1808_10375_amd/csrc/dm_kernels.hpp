@@ -105,106 +105,178 @@ __device__ __forceinline__ void block_sum2_rt(float& a, float& b, float* red) {
 }
 
 // ---------------------------------------------------------------------------
-// 2-D transform of one F x F frame held by F*F/16 threads, 16 values each.
-// Thread t = g*F + c.  Spatial layout: a[u1] = x[B*u1 + g][c].
+// 2-D transform of one F x F frame held by F*F/16 "virtual threads" of 16
+// values each; a real thread runs V of them (virtual thread t + v*NT, NT =
+// F*F/(16 V)), so every LDS exchange moves all V between one pair of barriers.
+// Virtual thread vt = g*F + c.  Spatial layout: a[u1] = x[B*u1 + g][c].
 // Spectral layout:  a[i*B + l2] = X[c][(g + B*i) + 16*l2].
 // buf: LDS, F rows of LD = F + 1 float2 (one padding column).
 // ---------------------------------------------------------------------------
-template <int F, int DIR>
+template <int F, int DIR, int V = 1>
 struct Frame2D {
   static constexpr int B = F / 16;
   static constexpr int NI = 16 / B;  // k1 values per thread after the exchange
   static constexpr int LD = F + 1;
+  static constexpr int GS = B / V;   // g step between a thread's virtual threads
 
-  // forward: spatial -> spectral
-  __device__ __forceinline__ static void fwd(float2 (&a)[16], float2* buf,
-                                             const float2* __restrict__ tw, int c, int g) {
+  // forward: spatial -> spectral; g is the first virtual thread's row group
+  __device__ __forceinline__ static void fwd(float2 (&a)[V][16], float2* buf,
+                                             const float2* __restrict__ tw, int c, int g0) {
     static_assert(DIR < 0, "fwd is the forward transform");
-    // columns: 16-point over u1
-    dft16<-1>(a);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int g = g0 + v * GS;
+      dft16<-1>(a[v]);
+      if constexpr (B > 1) {
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) a[v][k1] = twiddle<-1>(tw, g * k1, a[v][k1]);
+      }
+      if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+    }
     if constexpr (B > 1) {
-#pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, g * k1, a[k1]);
       __syncthreads();
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) buf[(k1 * B + g) * LD + c] = a[k1];
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) buf[(k1 * B + g0 + v * GS) * LD + c] = a[v][k1];
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
 #pragma unroll
-        for (int q = 0; q < B; ++q) a[i * B + q] = buf[((g + B * i) * B + q) * LD + c];
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+          for (int q = 0; q < B; ++q) a[v][i * B + q] = buf[((g + B * i) * B + q) * LD + c];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[v][i * B]);
+        if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+      }
     }
     // transpose to rows: Xc[(g + B i) + 16 k2][c] -> row c of the buffer
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) buf[((g + B * i) + 16 * k2) * LD + c] = a[i * B + k2];
-    __syncthreads();
-#pragma unroll
-    for (int v1 = 0; v1 < 16; ++v1) a[v1] = buf[c * LD + B * v1 + g];
-    // rows: 16-point over v1
-    dft16<-1>(a);
-    if constexpr (B > 1) {
-#pragma unroll
-      for (int l1 = 1; l1 < 16; ++l1) a[l1] = twiddle<-1>(tw, g * l1, a[l1]);
-      __syncthreads();
-#pragma unroll
-      for (int l1 = 0; l1 < 16; ++l1) buf[c * LD + l1 * B + g] = a[l1];
-      __syncthreads();
+    for (int v = 0; v < V; ++v) {
+      const int g = g0 + v * GS;
 #pragma unroll
       for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int q = 0; q < B; ++q) a[i * B + q] = buf[c * LD + (g + B * i) * B + q];
+        for (int k2 = 0; k2 < B; ++k2) buf[((g + B * i) + 16 * k2) * LD + c] = a[v][i * B + k2];
+    }
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
+    for (int v = 0; v < V; ++v) {
+      const int g = g0 + v * GS;
+#pragma unroll
+      for (int v1 = 0; v1 < 16; ++v1) a[v][v1] = buf[c * LD + B * v1 + g];
+      // rows: 16-point over v1
+      dft16<-1>(a[v]);
+      if constexpr (B > 1) {
+#pragma unroll
+        for (int l1 = 1; l1 < 16; ++l1) a[v][l1] = twiddle<-1>(tw, g * l1, a[v][l1]);
+      }
+      if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (B > 1) {
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int l1 = 0; l1 < 16; ++l1) buf[c * LD + l1 * B + g0 + v * GS] = a[v][l1];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int q = 0; q < B; ++q) a[v][i * B + q] = buf[c * LD + (g + B * i) * B + q];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[v][i * B]);
+        if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 
   // inverse (unnormalised): spectral -> spatial, exact mirror of fwd
-  __device__ __forceinline__ static void inv(float2 (&a)[16], float2* buf,
-                                             const float2* __restrict__ tw, int c, int g) {
+  __device__ __forceinline__ static void inv(float2 (&a)[V][16], float2* buf,
+                                             const float2* __restrict__ tw, int c, int g0) {
     static_assert(DIR > 0, "inv is the inverse transform");
     if constexpr (B > 1) {
 #pragma unroll
-      for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+      for (int v = 0; v < V; ++v) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) dftB<1, B>(&a[v][i * B]);
+        if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+      }
       __syncthreads();
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int q = 0; q < B; ++q) buf[c * LD + (g + B * i) * B + q] = a[v][i * B + q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
+#pragma unroll
+        for (int l1 = 0; l1 < 16; ++l1) a[v][l1] = buf[c * LD + l1 * B + g];
+#pragma unroll
+        for (int l1 = 1; l1 < 16; ++l1) a[v][l1] = twiddle<1>(tw, g * l1, a[v][l1]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      dft16<1>(a[v]);
+      if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int v1 = 0; v1 < 16; ++v1) buf[c * LD + B * v1 + g0 + v * GS] = a[v][v1];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int g = g0 + v * GS;
 #pragma unroll
       for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int q = 0; q < B; ++q) buf[c * LD + (g + B * i) * B + q] = a[i * B + q];
-      __syncthreads();
-#pragma unroll
-      for (int l1 = 0; l1 < 16; ++l1) a[l1] = buf[c * LD + l1 * B + g];
-#pragma unroll
-      for (int l1 = 1; l1 < 16; ++l1) a[l1] = twiddle<1>(tw, g * l1, a[l1]);
+        for (int k2 = 0; k2 < B; ++k2) a[v][i * B + k2] = buf[((g + B * i) + 16 * k2) * LD + c];
     }
-    dft16<1>(a);
-    __syncthreads();
-#pragma unroll
-    for (int v1 = 0; v1 < 16; ++v1) buf[c * LD + B * v1 + g] = a[v1];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) a[i * B + k2] = buf[((g + B * i) + 16 * k2) * LD + c];
     if constexpr (B > 1) {
 #pragma unroll
-      for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);
+      for (int v = 0; v < V; ++v) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) dftB<1, B>(&a[v][i * B]);
+        if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+      }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
 #pragma unroll
-        for (int q = 0; q < B; ++q) buf[((g + B * i) * B + q) * LD + c] = a[i * B + q];
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int q = 0; q < B; ++q) buf[((g + B * i) * B + q) * LD + c] = a[v][i * B + q];
+      }
       __syncthreads();
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) a[k1] = buf[(k1 * B + g) * LD + c];
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
 #pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, g * k1, a[k1]);
+        for (int k1 = 0; k1 < 16; ++k1) a[v][k1] = buf[(k1 * B + g) * LD + c];
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) a[v][k1] = twiddle<1>(tw, g * k1, a[v][k1]);
+      }
     }
-    dft16<1>(a);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      dft16<1>(a[v]);
+      if constexpr (V > 1) __builtin_amdgcn_sched_barrier(0);
+    }
   }
 };
 
@@ -234,12 +306,13 @@ __device__ __forceinline__ int xcd_slot(int b, int nblocks) {
   return (x < full) ? x * per + k : full * per + (x - full) * (per - 1) + k;
 }
 
-template <int F>
-__global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
+template <int F, int V>
+__global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
     const float2* __restrict__ tw, int M) {
   constexpr int B = F / 16;
-  constexpr int NT = F * B;
+  constexpr int NT = F * B / V;  // threads; each runs V virtual threads
+  constexpr int GS = B / V;      // row-group step between a thread's virtual threads
   constexpr int LD = F + 1;
   constexpr int FF = F * F;
   __shared__ float2 buf[F * LD];
@@ -262,44 +335,55 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
   const int H = sc.H, W = sc.W;
   const float beta = sc.beta;
   const int c = t % F;
-  const int g = wave_uniform_div<F>(t);
+  const int g0 = wave_uniform_div<F>(t);
   const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
   // buffers: this view's modes, the probe, the object, this view's scale
   const rsrc_t rpsi = make_rsrc(psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
   const rsrc_t rP = make_rsrc(P, (uint32_t)(M * FF * 8));
   const rsrc_t rO = make_rsrc(O, (uint32_t)((size_t)H * W * 8));
   const rsrc_t rg = make_rsrc(gscr + (size_t)j * FF, (uint32_t)(FF * 4));
-  // per-lane byte offsets (row g of each block of B rows, column c)
-  const int vF = (g * F + c) * 8;
-  const int vO = (g * W + c) * 8;
+  // per-lane byte offsets of the first virtual thread (row g0, column c);
+  // the other virtual threads and rows differ by wave-uniform offsets
+  const int vF = (g0 * F + c) * 8;
+  const int vO = (g0 * W + c) * 8;
   const int sO = (y0 * W + x0) * 8;
   const int vG = t * 4;
+  // byte offset of row B*u1 + v*GS relative to the first virtual thread's row
+  auto rowF = [&](int v, int u1) { return (B * u1 + v * GS) * F * 8; };
+  auto rowO = [&](int v, int u1) { return (B * u1 + v * GS) * W * 8; };
 
-  // F = 128 runs 1024 threads with at most 128 VGPRs each: the view is read
-  // again in the epilogue instead of being held through both transforms.
+  // The view is held in registers through both transforms when they fit
+  // (F < 128 with one virtual thread, or F = 128 with two virtual threads per
+  // 256-VGPR thread); otherwise it is read once more in the epilogue.
   constexpr bool kHold = (F < 128);
-  float2 a[16];
-  float2 hold[kHold ? 16 : 1];
+  float2 a[V][16];
+  float2 hold[kHold ? V : 1][kHold ? 16 : 1];
   {
-    float S[16];
+    float S[V][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) S[r] = 0.f;
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S[v][r] = 0.f;
 
     // ---- pass 1: mode sum of |DFT(2 phi - psi)|^2
     for (int m = 0; m < M; ++m) {
       const int sm = m * FF * 8;
 #pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) {
-        const int srow = u1 * B * F * 8;
-        const float2 ps = bload2(rpsi, vF, sm + srow);
-        const float2 phi = cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-        if constexpr (kHold) hold[u1] = ps;
-        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-      }
-      Frame2D<F, -1>::fwd(a, buf, twl, c, g);
+      for (int v = 0; v < V; ++v)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) S[r] += cabs2(a[r]);
+        for (int u1 = 0; u1 < 16; ++u1) {
+          const float2 ps = bload2(rpsi, vF, sm + rowF(v, u1));
+          const float2 phi =
+              cmul(bload2(rP, vF, sm + rowF(v, u1)), bload2(rO, vO, sO + rowO(v, u1)));
+          a[v][u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+          if constexpr (kHold) hold[kHold ? v : 0][kHold ? u1 : 0] = ps;
+          if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+      Frame2D<F, -1, V>::fwd(a, buf, twl, c, g0);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) S[v][r] += cabs2(a[v][r]);
     }
 
     // ---- modulus scale: stage I through LDS (padded rows), form g, park it
@@ -310,63 +394,80 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_fused(
     __syncthreads();
     const float inv_ff = 1.0f / (float)FF;
 #pragma unroll
-    for (int i = 0; i < 16 / B; ++i)
+    for (int v = 0; v < V; ++v) {
+      const int g = g0 + v * GS;
 #pragma unroll
-      for (int l2 = 0; l2 < B; ++l2) {
-        const int r = i * B + l2;
-        const int l = (g + B * i) + 16 * l2;
-        const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
-        const float sv = S[r];
-        S[r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
-      }
+      for (int i = 0; i < 16 / B; ++i)
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[r]), rg, vG, r * NT * 4, 0);
+        for (int l2 = 0; l2 < B; ++l2) {
+          const int r = i * B + l2;
+          const int l = (g + B * i) + 16 * l2;
+          const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
+          const float sv = S[v][r];
+          S[v][r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[v][r]), rg, vG,
+                                              (v * 16 + r) * NT * 4, 0);
   }
 
   // ---- pass 2: projected spectra back to views, modes in reverse order
-  float2 oacc[16];
+  float2 oacc[V][16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) oacc[v][r] = make_float2(0.f, 0.f);
   float e_d = 0.f, e_n = 0.f;
 
   for (int m = M - 1; m >= 0; --m) {
     const int sm = m * FF * 8;
     if (m != M - 1) {
 #pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int u1 = 0; u1 < 16; ++u1) {
+          const float2 ps = bload2(rpsi, vF, sm + rowF(v, u1));
+          const float2 phi =
+              cmul(bload2(rP, vF, sm + rowF(v, u1)), bload2(rO, vO, sO + rowO(v, u1)));
+          a[v][u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+          if constexpr (kHold) hold[kHold ? v : 0][kHold ? u1 : 0] = ps;
+          if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+      Frame2D<F, -1, V>::fwd(a, buf, twl, c, g0);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        a[v][r] = cscale(a[v][r], bload1(rg, vG, (v * 16 + r) * NT * 4));
+    Frame2D<F, 1, V>::inv(a, buf, twl, c, g0);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
       for (int u1 = 0; u1 < 16; ++u1) {
-        const int srow = u1 * B * F * 8;
-        const float2 ps = bload2(rpsi, vF, sm + srow);
-        const float2 phi =
-            cmul(bload2(rP, vF, sm + srow), bload2(rO, vO, sO + u1 * B * W * 8));
-        a[u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-        if constexpr (kHold) hold[u1] = ps;
+        const float2 pr = bload2(rP, vF, sm + rowF(v, u1));
+        const float2 phi = cmul(pr, bload2(rO, vO, sO + rowO(v, u1)));
+        const float2 ps = kHold ? hold[kHold ? v : 0][kHold ? u1 : 0]
+                                : bload2(rpsi, vF, sm + rowF(v, u1));
+        const float2 d = make_float2(beta * (a[v][u1].x - phi.x), beta * (a[v][u1].y - phi.y));
+        const float2 pn = cadd(ps, d);
+        bstore2(rpsi, pn, vF, sm + rowF(v, u1));
+        e_d += cabs2(d);
+        e_n += cabs2(pn);
+        oacc[v][u1] = cadd(oacc[v][u1], cmulc(pr, pn));
         if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
-      Frame2D<F, -1>::fwd(a, buf, twl, c, g);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], bload1(rg, vG, r * NT * 4));
-    Frame2D<F, 1>::inv(a, buf, twl, c, g);
-#pragma unroll
-    for (int u1 = 0; u1 < 16; ++u1) {
-      const int srow = u1 * B * F * 8;
-      const float2 pr = bload2(rP, vF, sm + srow);
-      const float2 phi = cmul(pr, bload2(rO, vO, sO + u1 * B * W * 8));
-      const float2 ps = kHold ? hold[kHold ? u1 : 0] : bload2(rpsi, vF, sm + srow);
-      const float2 d = make_float2(beta * (a[u1].x - phi.x), beta * (a[u1].y - phi.y));
-      const float2 pn = cadd(ps, d);
-      bstore2(rpsi, pn, vF, sm + srow);
-      e_d += cabs2(d);
-      e_n += cabs2(pn);
-      oacc[u1] = cadd(oacc[u1], cmulc(pr, pn));
-      if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
   }
 
   const rsrc_t ropart = make_rsrc(opart + (size_t)j * FF, (uint32_t)(FF * 8));
 #pragma unroll
-  for (int u1 = 0; u1 < 16; ++u1) bstore2(ropart, oacc[u1], vF, u1 * B * F * 8);
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int u1 = 0; u1 < 16; ++u1) bstore2(ropart, oacc[v][u1], vF, rowF(v, u1));
 
   block_sum2<NT>(e_d, e_n, red);
   if (t == 0) {

@@ -227,6 +227,19 @@ dm_status dm_scan_get_probe(dm_ctx* ctx, int32_t scan, void* dst_dev);
 dm_status dm_scan_error_history(dm_ctx* ctx, int32_t scan, int32_t first,
                                 int32_t count, dm_errors* out_host);
 
+/* ---- warm start ------------------------------------------------------------ */
+/* Replace the object with patches stitched by the object update (Section II,
+ * Eq. 5) applied to the exit waves psi_{j,k} = P_k * patch_j with the current
+ * probe; the paper allows initial guesses taken from pre-existing results
+ * (Section III).  Pixels under no window keep their value.  Then reset every
+ * view to psi = P * O[window] (the initial state of Section II).
+ *   patches_dev  complex64 [N][F][F], device, caller-owned; patch j is the
+ *                object guess under view j's window, indexed like the frame.
+ * Enqueued on the context's stream; the iteration counter is kept.
+ * DM_E_ARG: NULL or misaligned patches, or a scan index out of range. */
+dm_status dm_warm_start(dm_ctx* ctx, const void* patches_dev);
+dm_status dm_scan_warm_start(dm_ctx* ctx, int32_t scan, const void* patches_dev);
+
 /* ---- launch tuning -------------------------------------------------------- */
 dm_status dm_get_tuning(const dm_ctx* ctx, dm_tuning* out);
 

@@ -212,6 +212,32 @@ def loss_and_grads(params, x, target, levels: int = 4):
     return loss, backward(params, cache, dy, levels), y
 
 
+# ---------------------------------------------------------------------------
+# input and output maps between frames and the network
+# ---------------------------------------------------------------------------
+def preprocess(I):
+    """x[n][0] = log1p(2x2 block sums of max(I, 0)) / 10; I: [N][F][F]."""
+    I = np.maximum(np.asarray(I, dtype=np.float64), 0.0)
+    n, f, _ = I.shape
+    s = I.reshape(n, f // 2, 2, f // 2, 2).sum(axis=(2, 4))
+    return (np.log1p(s) / 10.0)[:, None]
+
+
+def patches(y):
+    """Complex patches [N][2S][2S] from y [N][2][S][S] (real, imaginary) by
+    bilinear 2x upsampling: output pixel u samples the input at u/2 - 1/4
+    (pixel centres), clamped to [0, S-1]."""
+    y = np.asarray(y, dtype=np.float64)
+    n, _, s, _ = y.shape
+    c = np.clip(np.arange(2 * s) / 2.0 - 0.25, 0.0, s - 1.0)
+    i0 = np.floor(c).astype(int)
+    i1 = np.minimum(i0 + 1, s - 1)
+    f = c - i0
+    z = y[:, 0] + 1j * y[:, 1]
+    rows = z[:, i0, :] * (1 - f)[None, :, None] + z[:, i1, :] * f[None, :, None]
+    return rows[:, :, i0] * (1 - f)[None, None, :] + rows[:, :, i1] * f[None, None, :]
+
+
 def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam update (Kingma & Ba), step t >= 1; returns new (params, m, v)."""
     out_p, out_m, out_v = [], [], []

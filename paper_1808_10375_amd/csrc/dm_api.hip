@@ -921,6 +921,45 @@ dm_status dm_scan_get_probe(dm_ctx* c, int32_t scan, void* dst) {
   return DM_OK;
 }
 
+dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
+  dm_status s = check_scan(c, scan);
+  if (s != DM_OK) return s;
+  if (!patches_dev || !aligned8(patches_dev)) {
+    c->err = "warm start needs an 8-byte aligned device array of patches";
+    return DM_E_ARG;
+  }
+  auto& S = c->scans[scan];
+  const ScanLayout& L = S.L;
+  const int FF = S.d.frame * S.d.frame;
+  const size_t total = (size_t)S.d.n_frames * FF;
+  hipLaunchKernelGGL(dmk::k_warm_opart, dim3((unsigned)std::min<size_t>((total + 255) / 256, 8192)),
+                     dim3(256), 0, c->stream, c->sat<float2>(scan, L.opart),
+                     c->sat<float>(scan, L.D), reinterpret_cast<const float2*>(patches_dev),
+                     S.d.n_frames, FF);
+  DM_LAUNCHED(c, "k_warm_opart");
+  // the object gather over this scan's tiles only: they are a contiguous
+  // range of the tile map
+  int first = 0;
+  for (int t = 0; t < scan; ++t) first += c->scans[t].ntiles;
+  if (c->tune.obj_tile == 16)
+    hipLaunchKernelGGL(dmk::k_object<16>, dim3(S.ntiles), dim3(256), 0, c->stream, c->scan_dev(),
+                       c->tmap() + first, S.d.frame);
+  else
+    hipLaunchKernelGGL(dmk::k_object<32>, dim3(S.ntiles), dim3(256), 0, c->stream, c->scan_dev(),
+                       c->tmap() + first, S.d.frame);
+  DM_LAUNCHED(c, "k_object (warm start)");
+  hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes), dim3(256), 0, c->stream,
+                     c->sat<float2>(scan, L.psi), c->sat<float2>(scan, L.P),
+                     c->sat<float2>(scan, L.O), c->sat<int>(scan, L.pos), S.d.n_modes,
+                     S.d.frame, S.d.obj_w);
+  DM_LAUNCHED(c, "k_init_psi");
+  return DM_OK;
+}
+
+dm_status dm_warm_start(dm_ctx* c, const void* patches_dev) {
+  return dm_scan_warm_start(c, 0, patches_dev);
+}
+
 dm_status dm_get_object(dm_ctx* c, void* dst) { return dm_scan_get_object(c, 0, dst); }
 dm_status dm_get_probe(dm_ctx* c, void* dst) { return dm_scan_get_probe(c, 0, dst); }
 

@@ -1013,4 +1013,20 @@ __global__ void k_fill_int(int* __restrict__ p, int n, int val) {
   if (i < n) p[i] = val;
 }
 
+// Warm start: per-view object numerators of the exit waves psi_{j,k} =
+// P_k * patch_j, i.e. sum_k conj(P_k) P_k patch_j = D * patch_j, so that the
+// object gather (Eq. 5) stitches the patches with the weights D.
+__global__ __launch_bounds__(256) void k_warm_opart(float2* __restrict__ opart,
+                                                    const float* __restrict__ D,
+                                                    const float2* __restrict__ patches, int N,
+                                                    int FF) {
+  const size_t total = (size_t)N * FF;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const float d = D[e % FF];
+    const float2 q = patches[e];
+    opart[e] = make_float2(d * q.x, d * q.y);
+  }
+}
+
 }  // namespace dmk

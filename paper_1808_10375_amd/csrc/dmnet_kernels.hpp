@@ -1,0 +1,319 @@
+// dmnet_kernels.hpp -- gfx950 kernels of the warm-start encoder-decoder:
+// direct 3x3 / 1x1 convolutions (bfloat16-stored weights, float32
+// accumulation) forward and data-gradient, weight/bias gradients by
+// fixed-order block reductions (no atomics), pooling, upsampling, ReLU mask,
+// MSE, Adam, input preprocessing and patch upsampling.  Activations are NCHW
+// float32 with a per-sample stride, so a tensor can be a channel slice of a
+// concatenation buffer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmn {
+
+__device__ __forceinline__ float bf16_bits_to_f(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// round to nearest bfloat16, ties to even (finite inputs)
+__device__ __forceinline__ uint16_t f_to_bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Convolution, forward (TRANS = false) or data gradient (TRANS = true).
+//   forward:  y[n][o][p] = b[o] + sum_c sum_t w[o][c][t] x[n][c][p + off_t]
+//   gradient: y[n][c][p] = sum_o sum_t w[o][c][K*K-1-t] x[n][o][p + off_t]
+//             (x is then the gradient of the forward output)
+// w has shape [w_cout][w_cin][K][K].  One thread per output pixel, COB
+// output channels per block row; weights are wave-uniform loads.
+// grid (ceil(H*W / blockDim), ceil(yc / COB), n)
+// ---------------------------------------------------------------------------
+template <int K, int COB, bool TRANS, bool FP32W>
+__global__ __launch_bounds__(256) void k_conv(const float* __restrict__ x, int xc, int H, int W,
+                                              long x_ns, const uint16_t* __restrict__ wb,
+                                              const float* __restrict__ wf,
+                                              const float* __restrict__ bias, int w_cin,
+                                              float* __restrict__ y, int yc, long y_ns,
+                                              int relu) {
+  constexpr int KK = K * K;
+  const int HW = H * W;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  const int i = p / W, j = p % W;
+  const int o0 = blockIdx.y * COB;
+  const int n = blockIdx.z;
+  const float* __restrict__ xn = x + (long)n * x_ns;
+  float acc[COB];
+#pragma unroll
+  for (int o = 0; o < COB; ++o) acc[o] = (!TRANS && bias && o0 + o < yc) ? bias[o0 + o] : 0.f;
+  for (int c = 0; c < xc; ++c) {
+    float xv[KK];
+#pragma unroll
+    for (int t = 0; t < KK; ++t) {
+      const int ii = i + t / K - K / 2, jj = j + t % K - K / 2;
+      xv[t] = ((unsigned)ii < (unsigned)H && (unsigned)jj < (unsigned)W)
+                  ? xn[(long)c * HW + ii * W + jj]
+                  : 0.f;
+    }
+#pragma unroll
+    for (int o = 0; o < COB; ++o) {
+      if (o0 + o < yc) {
+#pragma unroll
+        for (int t = 0; t < KK; ++t) {
+          const long wi = TRANS ? ((long)c * w_cin + (o0 + o)) * KK + (KK - 1 - t)
+                                : ((long)(o0 + o) * w_cin + c) * KK + t;
+          const float wv = FP32W ? wf[wi] : bf16_bits_to_f(wb[wi]);
+          acc[o] += wv * xv[t];
+        }
+      }
+    }
+  }
+  float* __restrict__ yn = y + (long)n * y_ns;
+#pragma unroll
+  for (int o = 0; o < COB; ++o)
+    if (o0 + o < yc) yn[(long)(o0 + o) * HW + p] = relu ? fmaxf(acc[o], 0.f) : acc[o];
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradient of a convolution:
+//   dw[o][c][t] = sum_n sum_p dz[n][o][p] x[n][c][p + off_t]
+//   db[o]       = sum_n sum_p dz[n][o][p]                (block row 0 only)
+// One block per (o, chunk of CIB input channels); each thread sums a strided
+// subset of positions, then the block adds the per-thread sums in thread
+// order.  grid (zc, ceil(xc / CIB)), 256 threads.
+// ---------------------------------------------------------------------------
+template <int K, int CIB>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x, int xc, int H,
+                                                    int W, long x_ns, const float* __restrict__ dz,
+                                                    long z_ns, int n_samples,
+                                                    float* __restrict__ dw,
+                                                    float* __restrict__ db) {
+  constexpr int KK = K * K;
+  constexpr int NV = CIB * KK + 1;
+  __shared__ float red[NV][257];
+  const int HW = H * W;
+  const int o = blockIdx.x;
+  const int c0 = blockIdx.y * CIB;
+  const int t = threadIdx.x;
+  float acc[CIB * KK];
+  float accb = 0.f;
+#pragma unroll
+  for (int q = 0; q < CIB * KK; ++q) acc[q] = 0.f;
+  const int total = n_samples * HW;
+  for (int pos = t; pos < total; pos += 256) {
+    const int n = pos / HW, p = pos % HW;
+    const int i = p / W, j = p % W;
+    const float g = dz[(long)n * z_ns + (long)o * HW + p];
+    accb += g;
+    const float* __restrict__ xn = x + (long)n * x_ns;
+#pragma unroll
+    for (int ci = 0; ci < CIB; ++ci) {
+      if (c0 + ci < xc) {
+#pragma unroll
+        for (int tt = 0; tt < KK; ++tt) {
+          const int ii = i + tt / K - K / 2, jj = j + tt % K - K / 2;
+          if ((unsigned)ii < (unsigned)H && (unsigned)jj < (unsigned)W)
+            acc[ci * KK + tt] += g * xn[(long)(c0 + ci) * HW + ii * W + jj];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CIB * KK; ++q) red[q][t] = acc[q];
+  red[NV - 1][t] = accb;
+  __syncthreads();
+  for (int q = t; q < NV; q += 256) {
+    float s = 0.f;
+    for (int k = 0; k < 256; ++k) s += red[q][k];
+    if (q == NV - 1) {
+      if (db && blockIdx.y == 0) db[o] = s;
+    } else {
+      const int ci = q / KK, tt = q % KK;
+      if (c0 + ci < xc) dw[((long)o * xc + c0 + ci) * KK + tt] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise pieces; grid-stride loops over n * C * H * W
+// ---------------------------------------------------------------------------
+// dst = 2x2 average of src (C channels, src H x W)
+__global__ void k_avgpool2(const float* __restrict__ src, long s_ns, float* __restrict__ dst,
+                           long d_ns, int C, int H, int W, int n) {
+  const int Ho = H / 2, Wo = W / 2;
+  const long per = (long)C * Ho * Wo, total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / per);
+    const long r = e % per;
+    const int c = (int)(r / (Ho * Wo)), q = (int)(r % (Ho * Wo));
+    const int i = q / Wo, j = q % Wo;
+    const float* s = src + nn * s_ns + (long)c * H * W + (2 * i) * W + 2 * j;
+    dst[nn * d_ns + (long)c * Ho * Wo + q] = 0.25f * (s[0] + s[1] + s[W] + s[W + 1]);
+  }
+}
+
+// dst (H x W) += gradient of the 2x2 average pooling whose output gradient is
+// g (H/2 x W/2)
+__global__ void k_avgpool2_bwd_add(const float* __restrict__ g, long g_ns,
+                                   float* __restrict__ dst, long d_ns, int C, int H, int W,
+                                   int n) {
+  const long per = (long)C * H * W, total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / per);
+    const long r = e % per;
+    const int c = (int)(r / (H * W)), q = (int)(r % (H * W));
+    const int i = q / W, j = q % W;
+    dst[nn * d_ns + r] += 0.25f * g[nn * g_ns + (long)c * (H / 2) * (W / 2) + (i / 2) * (W / 2) + j / 2];
+  }
+}
+
+// dst (2H x 2W) = nearest upsampling of src (H x W)
+__global__ void k_upsample2(const float* __restrict__ src, long s_ns, float* __restrict__ dst,
+                            long d_ns, int C, int H, int W, int n) {
+  const int Ho = 2 * H, Wo = 2 * W;
+  const long per = (long)C * Ho * Wo, total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / per);
+    const long r = e % per;
+    const int c = (int)(r / (Ho * Wo)), q = (int)(r % (Ho * Wo));
+    const int i = q / Wo, j = q % Wo;
+    dst[nn * d_ns + r] = src[nn * s_ns + (long)c * H * W + (i / 2) * W + j / 2];
+  }
+}
+
+// dst (H x W) = gradient of nearest upsampling: sum of the 4 children of g
+__global__ void k_upsample2_bwd(const float* __restrict__ g, long g_ns, float* __restrict__ dst,
+                                long d_ns, int C, int H, int W, int n) {
+  const long per = (long)C * H * W, total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / per);
+    const long r = e % per;
+    const int c = (int)(r / (H * W)), q = (int)(r % (H * W));
+    const int i = q / W, j = q % W;
+    const float* s = g + nn * g_ns + (long)c * 4 * H * W + (2 * i) * (2 * W) + 2 * j;
+    dst[nn * d_ns + r] = s[0] + s[1] + s[2 * W] + s[2 * W + 1];
+  }
+}
+
+// g *= (act > 0)
+__global__ void k_relu_mask(float* __restrict__ g, long g_ns, const float* __restrict__ act,
+                            long a_ns, long per, int n) {
+  const long total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / per);
+    const long r = e % per;
+    if (!(act[nn * a_ns + r] > 0.f)) g[nn * g_ns + r] = 0.f;
+  }
+}
+
+// dy = 2 (y - t) / denom over count elements, and per-block partial sums of
+// (y - t)^2 (denom: number of outputs the loss averages over)
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
+                                             const float* __restrict__ t, long count,
+                                             float denom, float* __restrict__ dy,
+                                             float* __restrict__ partial) {
+  __shared__ float red[256];
+  float s = 0.f;
+  const float k = 2.0f / denom;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < count; e += (long)gridDim.x * 256) {
+    const float d = y[e] - t[e];
+    s += d * d;
+    dy[e] = k * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_partials(const float* __restrict__ partial, int n, long count,
+                               float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    out[0] = (float)(s / (double)count);
+  }
+}
+
+// Adam with bias-corrected moments; refresh the bfloat16 copy
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, uint16_t* __restrict__ wb, long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const float ge = g[e];
+    const float me = b1 * m[e] + (1.f - b1) * ge;
+    const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    const float mh = me / c1, vh = ve / c2;
+    const float pe = p[e] - lr * mh / (sqrtf(vh) + eps);
+    p[e] = pe;
+    wb[e] = f_to_bf16_bits(pe);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ p, uint16_t* __restrict__ wb, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    wb[e] = f_to_bf16_bits(p[e]);
+}
+
+__global__ void k_fill(float* __restrict__ p, long n, float v) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// x[n][0][i][j] = log1p(sum of the 2x2 block of max(I, 0)) / 10
+__global__ void k_preprocess(const float* __restrict__ I, int F, int n, float* __restrict__ x) {
+  const int S = F / 2;
+  const long total = (long)n * S * S;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / (S * S));
+    const int q = (int)(e % (S * S));
+    const int i = q / S, j = q % S;
+    const float* b = I + (long)nn * F * F + (2 * i) * F + 2 * j;
+    const float s = fmaxf(b[0], 0.f) + fmaxf(b[1], 0.f) + fmaxf(b[F], 0.f) + fmaxf(b[F + 1], 0.f);
+    x[e] = log1pf(s) * 0.1f;
+  }
+}
+
+// complex patch [2S][2S] by bilinear 2x upsampling of y [2][S][S]
+__global__ void k_patches(const float* __restrict__ y, int S, int n, float2* __restrict__ out) {
+  const int P = 2 * S;
+  const long total = (long)n * P * P;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int nn = (int)(e / (P * P));
+    const int q = (int)(e % (P * P));
+    const int u = q / P, v = q % P;
+    const float sy = fminf(fmaxf(0.5f * u - 0.25f, 0.f), (float)(S - 1));
+    const float sx = fminf(fmaxf(0.5f * v - 0.25f, 0.f), (float)(S - 1));
+    const int i0 = (int)sy, j0 = (int)sx;
+    const int i1 = min(i0 + 1, S - 1), j1 = min(j0 + 1, S - 1);
+    const float fy = sy - i0, fx = sx - j0;
+    float r[2];
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const float* c = y + ((long)nn * 2 + ch) * S * S;
+      const float a = c[i0 * S + j0] * (1.f - fx) + c[i0 * S + j1] * fx;
+      const float b = c[i1 * S + j0] * (1.f - fx) + c[i1 * S + j1] * fx;
+      r[ch] = a * (1.f - fy) + b * fy;
+    }
+    out[e] = make_float2(r[0], r[1]);
+  }
+}
+
+}  // namespace dmn

@@ -40,7 +40,7 @@ EXPORTED = [
     "dm_free", "dm_status_str", "dm_last_error", "dm_phase_times",
     "dm_batch_workspace_bytes", "dm_batch_init", "dm_n_scans", "dm_scan_get_object",
     "dm_scan_get_probe", "dm_scan_error_history", "dm_get_tuning", "dm_set_tuning",
-    "dm_autotune",
+    "dm_autotune", "dm_warm_start", "dm_scan_warm_start",
 ]
 
 
@@ -133,6 +133,10 @@ def lib():
     L.dm_set_tuning.restype = i32
     L.dm_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(dm_tuning)]
     L.dm_autotune.restype = i32
+    L.dm_warm_start.argtypes = [vp, vp]
+    L.dm_warm_start.restype = i32
+    L.dm_scan_warm_start.argtypes = [vp, i32, vp]
+    L.dm_scan_warm_start.restype = i32
     L.dm_free.argtypes = [vp]
     L.dm_free.restype = None
     L.dm_status_str.argtypes = [i32]
@@ -309,6 +313,14 @@ def dm_autotune(ctx, reps: int = 5, cache_path: Optional[str] = None) -> dm_tuni
     return t
 
 
+def dm_warm_start(ctx, patches):
+    _check(lib().dm_warm_start(ctx, _ptr(patches)), ctx)
+
+
+def dm_scan_warm_start(ctx, scan: int, patches):
+    _check(lib().dm_scan_warm_start(ctx, int(scan), _ptr(patches)), ctx)
+
+
 def dm_free(ctx):
     if ctx:
         lib().dm_free(ctx)
@@ -385,6 +397,12 @@ class DMContext:
 
     def phase_times(self):
         return dm_phase_times(self.ctx)
+
+    def warm_start(self, patches):
+        """Stitch complex64 patches [N][F][F] (device) into the object."""
+        import torch
+        self._patches = patches.to(self.device, torch.complex64).contiguous()
+        dm_warm_start(self.ctx, self._patches)
 
     def tuning(self) -> dict:
         return dm_get_tuning(self.ctx).to_dict()
@@ -475,6 +493,13 @@ class DMBatch:
 
     def autotune(self, reps=5, cache_path=None) -> dict:
         return dm_autotune(self.ctx, reps, cache_path).to_dict()
+
+    def warm_start(self, scan: int, patches):
+        """Stitch complex64 patches [N_s][F][F] (device) into scan's object."""
+        import torch
+        p = patches.to(self.device, torch.complex64).contiguous()
+        self._keep.append(p)
+        dm_scan_warm_start(self.ctx, scan, p)
 
     @property
     def iterations(self) -> int:

@@ -142,3 +142,61 @@ def test_batch_init_bounds_reported_per_scan():
     st = L.dm_batch_init(ctypes.byref(ctx), 1, arr1, ptrs, pos_arr, ptrs, ptrs, 256,
                          dm.dm_batch_workspace_bytes([g]), None)
     assert st == dm.DM_E_ARG and "stream" in dm.dm_last_error(None)
+
+
+# ---- warm-start network (include/dmnet.h) --------------------------------
+NET_HEADER = os.path.join(ROOT, "include", "dmnet.h")
+
+
+def net_declared_functions():
+    text = open(NET_HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmnet_[a-z_]+)\s*\(", text)))
+
+
+def test_dmnet_header_binding_and_exports_agree():
+    from paper_1808_10375_amd import dmnet
+    assert net_declared_functions() == sorted(dmnet.EXPORTED)
+    L = ctypes.CDLL(dm.LIB_PATH)
+    for name in net_declared_functions():
+        assert hasattr(L, name), name
+    assert ctypes.sizeof(dmnet.dmnet_desc) == 40
+
+
+def test_dmnet_parameter_count_matches_oracle_layout():
+    from oracle import cnn_oracle
+    from paper_1808_10375_amd import dmnet
+    for c0, levels in ((32, 4), (4, 3), (2, 2), (3, 5)):
+        d = dmnet.make_desc(2, size=32, base_ch=c0, levels=levels)
+        assert dmnet.dmnet_n_params(d) == cnn_oracle.n_params(c0, levels)
+    assert dmnet.dmnet_n_params(dmnet.make_desc(1)) == cnn_oracle.n_params(32, 4)
+
+
+def test_dmnet_rejects_invalid_descriptions():
+    from paper_1808_10375_amd import dmnet
+    good = dmnet.make_desc(4, size=64)
+    assert dmnet.dmnet_workspace_bytes(good) > 4 * 2 * 64 * 64 * 4
+    for bad in (dict(batch=0), dict(size=36), dict(levels=1), dict(levels=7),
+                dict(base_ch=0), dict(lr=0.0), dict(beta1=1.0), dict(flags=2)):
+        kw = dict(batch=4, size=64)
+        kw.update(bad)
+        d = dmnet.make_desc(**kw)
+        assert dmnet.dmnet_workspace_bytes(d) == 0, bad
+        assert dmnet.dmnet_n_params(d) == 0, bad
+    L = dmnet.lib()
+    net = ctypes.c_void_p()
+    need = dmnet.dmnet_workspace_bytes(good)
+    assert L.dmnet_create(ctypes.byref(net), ctypes.byref(good), None, need, None) == dm.DM_E_ARG
+    assert L.dmnet_create(ctypes.byref(net), ctypes.byref(good), 256, need - 1,
+                          None) == dm.DM_E_WORKSPACE
+    assert L.dmnet_create(ctypes.byref(net), ctypes.byref(good), 264, need,
+                          None) == dm.DM_E_ARG  # misaligned workspace
+    assert not net.value
+    assert L.dmnet_forward(None, 256, 256, 1) == dm.DM_E_ARG
+    L.dmnet_free(None)
+
+
+def test_warm_start_on_null_context():
+    L = dm.lib()
+    assert L.dm_warm_start(None, 256) == dm.DM_E_ARG
+    assert L.dm_scan_warm_start(None, 0, 256) == dm.DM_E_ARG

@@ -78,3 +78,34 @@ def test_bf16_rounding_ties_to_even():
     assert r[2] == 1.0 + 2 ** -6             # halfway, rounds up to even
     assert r[3] == -2.5
     assert abs(r[4] - 3.0e-3) <= 2 ** -8 * 3.0e-3  # half an ulp (7 stored bits)
+
+
+def test_preprocess_constant_frames_and_clipping():
+    I = np.full((2, 8, 8), 3.0)
+    I[1] = -1.0                                 # negative counts count as zero
+    x = net.preprocess(I)
+    assert x.shape == (2, 1, 4, 4)
+    assert np.allclose(x[0], np.log(13.0) / 10.0, atol=1e-15)
+    assert np.all(x[1] == 0.0)
+    J = np.zeros((1, 4, 4))
+    J[0, 2, 3] = np.e - 1.0                     # one count in block (1, 1)
+    x = net.preprocess(J)[0, 0]
+    assert abs(x[1, 1] - 0.1) < 1e-15 and np.count_nonzero(x) == 1
+
+
+def test_patches_reproduce_constants_and_interior_linear_ramps():
+    s = 6
+    a = np.arange(s, dtype=float)
+    y = np.zeros((1, 2, s, s))
+    y[0, 0] = 2.0 + 0.5 * a[:, None] - 0.25 * a[None, :]
+    y[0, 1] = -1.0
+    z = net.patches(y)[0]
+    # bilinear interpolation is exact for affine fields away from the clamp
+    u = np.arange(1, 2 * s - 1)
+    c = u / 2.0 - 0.25
+    ref = 2.0 + 0.5 * c[:, None] - 0.25 * c[None, :]
+    assert np.max(np.abs(z.real[1:-1, 1:-1] - ref)) < 1e-13
+    assert np.all(z.imag == -1.0)
+    # the clamped border rows repeat the first input row
+    assert np.allclose(z.real[0], z.real[0, :] * 0 + (2.0 + 0.0 - 0.25 * np.clip(
+        np.arange(2 * s) / 2.0 - 0.25, 0, s - 1)))

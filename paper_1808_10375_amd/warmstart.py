@@ -1,0 +1,332 @@
+"""Learned warm start: training pairs from the DM solver, training of the
+encoder-decoder on the GPU, and the warm-versus-cold comparison.
+
+The paper allows the initial probe and object to come from pre-existing
+results (Section III).  Here the pre-existing results are DM reconstructions
+of synthetic scans: a network learns to map one diffraction frame to the
+object under its window, and its patches, stitched with the object update
+of Eq. 5, replace the flat initial object.  Plain DM from the flat object
+stays the fallback and the judge.
+
+Every arithmetic step of the reconstruction and of the network runs in
+libdm's kernels (dm.py, dmnet.py).  Host code here only prepares training
+targets from reconstructed objects (global phase and scale normalisation,
+window extraction, 2x2 binning) and bookkeeps.
+
+    python -m paper_1808_10375_amd.warmstart --out report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import synth
+
+FRAME = 128
+NET_SIZE = FRAME // 2
+MODE_WEIGHTS = [1.0, 0.5, 0.25]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# training data
+# ---------------------------------------------------------------------------
+def training_scan(seed: int, n_frames: int = 256, obj: int = 384) -> synth.Scan:
+    """A scan of the held-out family (3 HG modes, 128x128 frames, Fermat
+    spiral of 10 px mean step, 1e5 photons) on a smaller object."""
+    return synth.spiral_scan(seed, n_frames, 3, MODE_WEIGHTS, frame=FRAME, obj=obj,
+                             name=f"warm_train.{seed}")
+
+
+def illumination(P0: np.ndarray, pos: np.ndarray, shape) -> np.ndarray:
+    """sum_j sum_k |P0_k|^2 placed at every window (the Eq. 5 weights)."""
+    D = np.sum(np.abs(P0.astype(np.complex128)) ** 2, axis=0)
+    f = D.shape[0]
+    acc = np.zeros(shape)
+    for y, x in pos:
+        acc[y:y + f, x:x + f] += D
+    return acc
+
+
+def normalise_object(O: np.ndarray, weight: np.ndarray) -> np.ndarray:
+    """Remove the global factor c of the (P, O) -> (cP, O/c) ambiguity: over
+    well-lit pixels the mean of O becomes real and positive and its RMS
+    amplitude 1 (the scale the flat initial object assumes)."""
+    lit = weight >= 0.1 * weight.max()
+    c = np.mean(O[lit])
+    rms = math.sqrt(float(np.mean(np.abs(O[lit]) ** 2)))
+    return O * (np.conj(c) / abs(c)) / rms
+
+
+def patch_targets(O: np.ndarray, pos: np.ndarray, f: int = FRAME) -> np.ndarray:
+    """[N][2][f/2][f/2] float32: 2x2 averages of the object under each window."""
+    out = np.empty((len(pos), 2, f // 2, f // 2), dtype=np.float32)
+    for j, (y, x) in enumerate(pos):
+        w = O[y:y + f, x:x + f].reshape(f // 2, 2, f // 2, 2).mean(axis=(1, 3))
+        out[j, 0] = w.real
+        out[j, 1] = w.imag
+    return out
+
+
+def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
+               group: int = 16, net=None, device="cuda:0"):
+    """(x [P][1][64][64], target [P][2][64][64]) on the device, from DM runs of
+    `n_iter` iterations on the scans of `seeds`, `group` scans per batch."""
+    import torch
+    from .dm import DMBatch
+    xs, ts = [], []
+    for g0 in range(0, len(seeds), group):
+        t0 = time.time()
+        scans = [training_scan(s, n_frames, obj) for s in seeds[g0:g0 + group]]
+        t1 = time.time()
+        batch = DMBatch([dict(I=s.I, pos=s.pos, P0=s.P0, O0=s.O0) for s in scans],
+                        device=device)
+        batch.iterate(n_iter)
+        for k, s in enumerate(scans):
+            O = batch.object(k).cpu().numpy().astype(np.complex128)
+            w = illumination(s.P0, s.pos, O.shape)
+            t = patch_targets(normalise_object(O, w), s.pos)
+            I = torch.as_tensor(s.I).to(device)
+            xs.append(net.preprocess(I))
+            ts.append(torch.as_tensor(t).to(device))
+        batch.free()
+        log(f"pairs: scans {g0}..{g0 + len(scans) - 1}: generate {t1 - t0:.1f} s, "
+            f"DM {n_iter} it + targets {time.time() - t1:.1f} s")
+    return torch.cat(xs), torch.cat(ts)
+
+
+# ---------------------------------------------------------------------------
+# training
+# ---------------------------------------------------------------------------
+def train(net, x, t, x_val, t_val, epochs: int, batch: int, seed: int = 0,
+          log_every: int = 200):
+    """Adam over shuffled minibatches; returns the history of losses."""
+    import torch
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    n = x.shape[0]
+    hist = []
+    step = 0
+    t_start = time.time()
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(x.device)
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            want = (step % log_every == 0)
+            loss = net.train_step(x[idx], t[idx], want_loss=want)
+            if want:
+                hist.append({"step": step, "loss": loss})
+                log(f"train step {step} epoch {ep} loss {loss:.5f} "
+                    f"({time.time() - t_start:.0f} s)")
+            step += 1
+        vl = validation_loss(net, x_val, t_val, batch)
+        hist.append({"step": step, "epoch": ep, "val_loss": vl})
+        log(f"epoch {ep}: validation loss {vl:.5f}")
+    return hist, step, time.time() - t_start
+
+
+def validation_loss(net, x, t, batch):
+    tot, cnt = 0.0, 0
+    for b0 in range(0, x.shape[0] - batch + 1, batch):
+        loss, _ = net.loss_grad(x[b0:b0 + batch], t[b0:b0 + batch])
+        tot += loss
+        cnt += 1
+    return tot / max(cnt, 1)
+
+
+def predict_patches(net, I, batch: int):
+    """Complex patches [N][F][F] for the frames I [N][F][F] (device)."""
+    import torch
+    out = torch.empty((I.shape[0], I.shape[1], I.shape[2]), dtype=torch.complex64,
+                      device=I.device)
+    for b0 in range(0, I.shape[0], batch):
+        x = net.preprocess(I[b0:b0 + batch])
+        out[b0:b0 + batch] = net.patches(net.forward(x))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# warm versus cold
+# ---------------------------------------------------------------------------
+def object_error(O: np.ndarray, O_true: np.ndarray, weight: np.ndarray) -> float:
+    """Relative error of O against the truth over well-lit pixels, after the
+    best complex scale factor."""
+    lit = weight >= 0.1 * weight.max()
+    a, b = O[lit].astype(np.complex128), O_true[lit].astype(np.complex128)
+    c = np.vdot(a, b) / np.vdot(a, a)
+    return float(np.linalg.norm(c * a - b) / np.linalg.norm(b))
+
+
+def first_at_or_below(errs, level):
+    for k, e in enumerate(errs):
+        if e <= level:
+            return k + 1
+    return None
+
+
+def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1, 10, 50)):
+    """Run the scans as one batch from the flat object (cold) and from the
+    stitched patches (warm), with the same initial probe; report the error
+    histories and iterations to fixed error levels."""
+    import torch
+    from .dm import DMBatch, DM_FLAG_GRAPH
+    res = {}
+    weights = [illumination(s.P0, s.pos, s.O0.shape) for s in scans]
+    stream = torch.cuda.Stream(device=device)
+    for form in ("cold", "warm"):
+        with torch.cuda.stream(stream):
+            b = DMBatch([dict(I=s.I, pos=s.pos, P0=s.P0, O0=s.O0) for s in scans],
+                        flags=DM_FLAG_GRAPH, stream=stream, device=device)
+            t0 = time.time()
+            if form == "warm":
+                # the network runs on its own stream: synchronise around it
+                for k, s in enumerate(scans):
+                    torch.cuda.synchronize(device)
+                    I = torch.as_tensor(s.I).to(device)
+                    p = predict_patches(net, I, batch)
+                    torch.cuda.synchronize(device)
+                    b.warm_start(k, p)
+                torch.cuda.synchronize(device)
+            t_init = time.time() - t0
+            obj_err = {0: [object_error(b.object(k).cpu().numpy(), s.O_true, weights[k])
+                           for k, s in enumerate(scans)]}
+            done = 0
+            for c in list(checkpoints) + [n_iter]:
+                if c > done:
+                    b.iterate(c - done)
+                    done = c
+                    obj_err[c] = [object_error(b.object(k).cpu().numpy(), s.O_true, weights[k])
+                                  for k, s in enumerate(scans)]
+            errs = [[e["eps_probe"] for e in b.error_history(k)] for k in range(len(scans))]
+            b.free()
+        res[form] = {"err": errs, "obj_err": obj_err, "init_s": t_init}
+    out = {"n_iter": n_iter, "scans": len(scans), "per_scan": []}
+    for k in range(len(scans)):
+        ec, ew = res["cold"]["err"][k], res["warm"]["err"][k]
+        level = 1.1 * ec[-1]
+        row = {
+            "frames": int(scans[k].I.shape[0]),
+            "cold_final_err": ec[-1], "warm_final_err": ew[-1],
+            "iters_to_1e-3": {"cold": first_at_or_below(ec, 1e-3),
+                              "warm": first_at_or_below(ew, 1e-3)},
+            "iters_to_1.1x_cold_final": {"cold": first_at_or_below(ec, level),
+                                         "warm": first_at_or_below(ew, level)},
+            "object_error": {f: {str(c): res[f]["obj_err"][c][k] for c in res[f]["obj_err"]}
+                             for f in ("cold", "warm")},
+        }
+        out["per_scan"].append(row)
+    out["warm_init_s"] = res["warm"]["init_s"]
+
+    def med(f, key):
+        v = [r[key][f] for r in out["per_scan"]]
+        v = [x for x in v if x is not None]
+        return float(np.median(v)) if v else None
+    out["median"] = {
+        key: {f: med(f, key) for f in ("cold", "warm")}
+        for key in ("iters_to_1e-3", "iters_to_1.1x_cold_final")}
+    out["median_object_error"] = {
+        f: {str(c): float(np.median(res[f]["obj_err"][c])) for c in res[f]["obj_err"]}
+        for f in ("cold", "warm")}
+    return out
+
+
+def layer_shapes(c0: int = 32, levels: int = 4):
+    """(cout, cin, k) of every convolution in the parameter order of dmnet.h."""
+    ch = [c0 << l for l in range(levels)]
+    out, prev = [], 1
+    for l in range(levels):
+        out += [(ch[l], prev, 3), (ch[l], ch[l], 3)]
+        prev = ch[l]
+    for l in range(levels - 2, -1, -1):
+        out += [(ch[l], ch[l + 1] + ch[l], 3), (ch[l], ch[l], 3)]
+    out.append((2, ch[0], 1))
+    return out
+
+
+def initial_params(seed: int, c0: int = 32, levels: int = 4) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases, flat float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci, k in layer_shapes(c0, levels):
+        parts.append((rng.standard_normal(co * ci * k * k) * math.sqrt(2.0 / (ci * k * k))))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--train-scans", type=int, default=96)
+    ap.add_argument("--val-scans", type=int, default=8)
+    ap.add_argument("--train-frames", type=int, default=256)
+    ap.add_argument("--train-obj", type=int, default=384)
+    ap.add_argument("--dm-iters", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-iters", type=int, default=200)
+    ap.add_argument("--eval-scans", type=int, default=16)
+    ap.add_argument("--eval-sizes", type=str, default="",
+                    help="comma-separated frame counts instead of U{200..3000}")
+    ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--save-params", type=str, default="")
+    ap.add_argument("--load-params", type=str, default="")
+    a = ap.parse_args(argv)
+    import torch
+    from .dmnet import DMNet
+    dev = "cuda:0"
+    net = DMNet(a.batch, size=NET_SIZE, base_ch=32, levels=4, lr=a.lr, device=dev)
+    report = {"network": {"levels": 4, "channels": [32, 64, 128, 256],
+                          "params": net.n_params, "input": [1, NET_SIZE, NET_SIZE],
+                          "weights": "bf16 (fp32 master)", "accumulate": "fp32"}}
+    if a.load_params:
+        net.set_params(np.load(a.load_params, allow_pickle=False))
+        report["training"] = {"loaded": a.load_params}
+    else:
+        net.set_params(initial_params(10000))
+        t0 = time.time()
+        seeds = list(range(10000, 10000 + a.train_scans))
+        vseeds = list(range(20000, 20000 + a.val_scans))
+        x, t = make_pairs(seeds, a.dm_iters, a.train_frames, a.train_obj, net=net, device=dev)
+        xv, tv = make_pairs(vseeds, a.dm_iters, a.train_frames, a.train_obj, net=net,
+                            device=dev)
+        t_pairs = time.time() - t0
+        log(f"pairs: {x.shape[0]} training, {xv.shape[0]} validation ({t_pairs:.0f} s)")
+        v0 = validation_loss(net, xv, tv, a.batch)
+        hist, steps, t_train = train(net, x, t, xv, tv, a.epochs, a.batch)
+        report["training"] = {
+            "scans": a.train_scans, "frames_per_scan": a.train_frames,
+            "object": a.train_obj, "dm_iters": a.dm_iters, "pairs": int(x.shape[0]),
+            "validation_pairs": int(xv.shape[0]), "epochs": a.epochs, "batch": a.batch,
+            "lr": a.lr, "steps": steps, "pairs_s": t_pairs, "train_s": t_train,
+            "samples_per_s": steps * a.batch / t_train, "val_loss_initial": v0,
+            "history": hist}
+        # a target that predicts the flat initial object (1 + 0i) everywhere
+        flat = torch.zeros_like(tv)
+        flat[:, 0] = 1.0
+        report["training"]["val_loss_flat_object"] = float(torch.mean((flat - tv) ** 2))
+        del x, t
+        if a.save_params:
+            np.save(a.save_params, net.params().cpu().numpy())
+    sizes = ([int(v) for v in a.eval_sizes.split(",")] if a.eval_sizes
+             else synth.uneven_scan_sizes(1000, a.eval_scans))
+    t0 = time.time()
+    scans = synth.uneven_spirals_128(1000, len(sizes), sizes)
+    log(f"evaluation scans generated ({time.time() - t0:.0f} s): {sizes}")
+    report["evaluation"] = compare(net, scans, a.eval_iters, a.batch, dev)
+    line = json.dumps(report)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(line + "\n")
+    print(json.dumps({"median": report["evaluation"]["median"],
+                      "median_object_error": report["evaluation"]["median_object_error"]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -73,10 +73,16 @@ typedef enum {
 
 typedef enum {
   DM_FP32_FFT = 0,        /* FP32 radix FFTs on the vector ALUs             */
-  DM_BF16X3_DFT = 1       /* F = 128 only: each 2-D DFT as two dense GEMMs on
-                             MFMA with BF16 operands split hi + lo (3 terms)
-                             and FP32 accumulation; modulus, norms and the
-                             object normaliser stay FP32/FP64             */
+  DM_BF16X3_DFT = 1       /* F = 128 and M <= 8 only (else
+                             DM_E_UNSUPPORTED): each 2-D DFT as dense
+                             complex matrix products with the DFT matrix on
+                             MFMA, every real product split into
+                             hi*hi + hi*lo + lo*hi of BF16 pieces, FP32
+                             accumulation; the modulus scale, error norms
+                             and updates stay FP32 and the object
+                             normaliser sum_j sum_k |P_k|^2 accumulates in
+                             FP64 (as on every path).  Uses a spectrum
+                             buffer; DM_FLAG_MULTIPASS has no effect.     */
 } dm_precision;
 
 /* dm_desc.flags bits */

@@ -15,6 +15,7 @@
 
 #include "../../include/dm.h"
 #include "dm_kernels.hpp"
+#include "dm_mfma.hpp"
 
 using dmk::DevErrors;
 using dmk::ScanDev;
@@ -38,15 +39,17 @@ int default_chunks(int F) {
   return std::max(1, std::min(C, DM_MAX_PROBE_CHUNKS));
 }
 
+bool is_bf16x3(const dm_desc& d) { return d.precision == DM_BF16X3_DFT; }
+
 bool has_spectrum_buffer(const dm_desc& d) {
-  return d.frame == 256 || (d.flags & DM_FLAG_MULTIPASS);
+  return d.frame == 256 || (d.flags & DM_FLAG_MULTIPASS) || is_bf16x3(d);
 }
 
 dm_tuning default_tuning(const dm_desc& d) {
   dm_tuning t{};
   t.obj_tile = 16;
   t.probe_chunks = default_chunks(d.frame);
-  t.multipass = has_spectrum_buffer(d) ? 1 : 0;
+  t.multipass = (has_spectrum_buffer(d) && !is_bf16x3(d)) ? 1 : 0;
   return t;
 }
 
@@ -83,6 +86,8 @@ ScanLayout scan_layout(const dm_desc& d) {
   ScanLayout L{};
   const size_t N = d.n_frames, M = d.n_modes, F = d.frame, FF = F * F;
   const size_t c8 = 8;
+  // eps_psi partial sums per view: 1 (fused), F / row block (three-kernel
+  // FFT path), 2 (BF16x3 path, two row halves)
   L.ntiles16 = tiles_for(d.obj_h, d.obj_w, 16);  // the larger of the two tile counts
   L.nnz16 = std::max(nnz_bound(d, 16), nnz_bound(d, 32));
   L.n_psi_parts_fused = (int)N;
@@ -102,7 +107,8 @@ ScanLayout scan_layout(const dm_desc& d) {
   L.D = take(FF * 4);
   L.num_part = take((size_t)DM_MAX_PROBE_CHUNKS * M * FF * c8);
   L.den_part = take((size_t)DM_MAX_PROBE_CHUNKS * FF * 4);
-  L.err_psi = take((size_t)std::max(L.n_psi_parts_fused, L.n_psi_parts_multi) * 2 * 4);
+  L.err_psi = take((size_t)std::max({L.n_psi_parts_fused, L.n_psi_parts_multi, 2 * (int)N}) *
+                   2 * 4);
   L.err_obj = take((size_t)L.ntiles16 * 2 * 4);
   L.err_probe = take((size_t)n_pblk((int)F) * M * 2 * 4);
   L.ring = take(sizeof(DevErrors) * dmk::kRing);
@@ -116,7 +122,7 @@ ScanLayout scan_layout(const dm_desc& d) {
 }
 
 struct CtxLayout {
-  size_t scans, vmap, tmap, cmap, tw, flags, header;
+  size_t scans, vmap, tmap, cmap, tw, wf, flags, header;
   std::vector<size_t> scan_base;
   std::vector<ScanLayout> sl;
   size_t total;
@@ -140,6 +146,7 @@ CtxLayout ctx_layout(int n_scans, const dm_desc* d) {
   C.tmap = take(sizeof(int2) * tiles);
   C.cmap = take(sizeof(int2) * (size_t)DM_MAX_PROBE_CHUNKS * n_scans);
   C.tw = take(sizeof(float2) * d[0].frame);
+  C.wf = is_bf16x3(d[0]) ? take(sizeof(uint4) * dmk::kMfWords) : 0;
   C.flags = take(sizeof(int));
   C.header = off;
   for (int s = 0; s < n_scans; ++s) {
@@ -166,8 +173,12 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     why = "unknown precision";
     return DM_E_UNSUPPORTED;
   }
-  if (d->precision == DM_BF16X3_DFT) {
-    why = "the BF16x3 DFT form is not built into this library";
+  if (d->precision == DM_BF16X3_DFT && d->frame != dmk::kMfF) {
+    why = "the BF16x3 DFT form is built for 128 x 128 frames";
+    return DM_E_UNSUPPORTED;
+  }
+  if (d->precision == DM_BF16X3_DFT && d->n_modes > dmk::kMfMaxModes) {
+    why = "the BF16x3 DFT form takes at most 8 modes";
     return DM_E_UNSUPPORTED;
   }
   if (d->flags & ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH)) {
@@ -258,6 +269,8 @@ struct dm_ctx {
   int2* tmap() { return at<int2>(CL.tmap); }
   int2* cmap() { return at<int2>(CL.cmap); }
   float2* tw() { return at<float2>(CL.tw); }
+  const uint4* wf() { return at<uint4>(CL.wf); }
+  bool bf16x3() const { return is_bf16x3(scans[0].d); }
   int* flags_dev() { return at<int>(CL.flags); }
 };
 
@@ -417,7 +430,9 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
     v.ntiles = S.ntiles;
     v.C = S.C;
     v.chunk = S.chunk;
-    v.n_psi_parts = t.multipass ? L.n_psi_parts_multi : L.n_psi_parts_fused;
+    v.n_psi_parts = is_bf16x3(S.d)  ? 2 * S.d.n_frames
+                    : t.multipass   ? L.n_psi_parts_multi
+                                    : L.n_psi_parts_fused;
     v.beta = S.d.beta;
     v.pad = 0;
     for (int i = 0; i < S.ntiles; ++i) tmap.push_back(make_int2(s, i));
@@ -503,7 +518,90 @@ dm_status launch_views_multipass(dm_ctx* c) {
   return DM_OK;
 }
 
+// BF16x3 form: three persistent kernels, one block per CU, each holding the
+// split DFT matrix in LDS
+constexpr size_t kMfLdsW = sizeof(uint4) * dmk::kMfWords;
+constexpr size_t kMfLdsCols = kMfLdsW + 4 * dmk::kMfKs * 64 * 16;
+
+hipError_t set_mfma_lds() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dmk::k_mf_rows_fwd),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfLdsW);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(dmk::k_mf_cols),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfLdsCols);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(dmk::k_mf_rows_inv),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMfLdsW);
+  return e;
+}
+
+// The split DFT matrix in B-fragment order (see dm_mfma.hpp): W[a][b] =
+// exp(-2 pi i ab / F) in double, rounded to float, split into bfloat16 hi
+// and lo = bf16(x - hi), both rounded to nearest even.
+std::vector<uint4> mfma_dft_table() {
+  constexpr int F = dmk::kMfF;
+  auto rne = [](float f) -> uint32_t {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  };
+  auto bf = [](uint32_t h) -> float {
+    const uint32_t u = h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+  };
+  std::vector<uint16_t> half(4 * (size_t)dmk::kMfFrag * 8);
+  const double pi = 3.14159265358979323846;
+  for (int ks = 0; ks < dmk::kMfKs; ++ks)
+    for (int nt = 0; nt < dmk::kMfNt; ++nt)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 8; ++e) {
+          const int k = 32 * ks + 8 * (lane / 16) + e, n = 16 * nt + lane % 16;
+          const double ang = -2.0 * pi * (double)((k * n) % F) / (double)F;
+          const float v[2] = {(float)std::cos(ang), (float)std::sin(ang)};
+          for (int part = 0; part < 2; ++part) {
+            const uint32_t hi = rne(v[part]);
+            const uint32_t lo = rne(v[part] - bf(hi));
+            const size_t slot = (((size_t)ks * dmk::kMfNt + nt) * 64 + lane) * 8 + e;
+            half[(size_t)(2 * part) * dmk::kMfFrag * 8 + slot] = (uint16_t)hi;
+            half[(size_t)(2 * part + 1) * dmk::kMfFrag * 8 + slot] = (uint16_t)lo;
+          }
+        }
+  std::vector<uint4> out(dmk::kMfWords);
+  std::memcpy(out.data(), half.data(), out.size() * sizeof(uint4));
+  return out;
+}
+
+int mfma_grid(dm_ctx* c, int items) {
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        v > 0)
+      cus = v;
+  }
+  (void)c;
+  return std::max(1, std::min(items, cus));
+}
+
+dm_status launch_views_mfma(dm_ctx* c) {
+  const int M = c->M, nv = c->total_views;
+  hipLaunchKernelGGL(dmk::k_mf_rows_fwd, dim3(mfma_grid(c, nv * M)), dim3(256), kMfLdsW,
+                     c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
+  DM_LAUNCHED(c, "k_mf_rows_fwd");
+  hipLaunchKernelGGL(dmk::k_mf_cols, dim3(mfma_grid(c, nv * dmk::kMfNt)), dim3(256), kMfLdsCols,
+                     c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
+  DM_LAUNCHED(c, "k_mf_cols");
+  hipLaunchKernelGGL(dmk::k_mf_rows_inv, dim3(mfma_grid(c, nv * 2)), dim3(256), kMfLdsW,
+                     c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
+  DM_LAUNCHED(c, "k_mf_rows_inv");
+  return DM_OK;
+}
+
 dm_status launch_views(dm_ctx* c) {
+  if (c->bf16x3()) return launch_views_mfma(c);
   if (!c->tune.multipass) {
     switch (c->F) {
       case 16: return launch_views_fused<16>(c);
@@ -687,6 +785,13 @@ dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const floa
   std::vector<float2> tw = twiddles(c->F);
   INIT_HIP(hipMemcpyAsync(c->tw(), tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice,
                           c->stream));
+  std::vector<uint4> wtab;
+  if (c->bf16x3()) {
+    wtab = mfma_dft_table();
+    INIT_HIP(hipMemcpyAsync(const_cast<uint4*>(c->wf()), wtab.data(), wtab.size() * sizeof(uint4),
+                            hipMemcpyHostToDevice, c->stream));
+    INIT_HIP(set_mfma_lds());
+  }
   INIT_HIP(hipMemcpyAsync(c->vmap(), vmap.data(), vmap.size() * sizeof(int2),
                           hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(), 1, 0);
@@ -760,8 +865,8 @@ std::string tune_key(dm_ctx* c) {
   int nb = 0;
   while ((1 << (nb + 1)) <= c->total_views) ++nb;
   char k[200];
-  snprintf(k, sizeof k, "%s:F%d:M%d:N2^%d:S%zu:flags%u", arch.c_str(), c->F, c->M, nb,
-           c->scans.size(), c->flags & DM_FLAG_MULTIPASS);
+  snprintf(k, sizeof k, "%s:F%d:M%d:N2^%d:S%zu:flags%u:prec%d", arch.c_str(), c->F, c->M, nb,
+           c->scans.size(), c->flags & DM_FLAG_MULTIPASS, (int)c->scans[0].d.precision);
   return k;
 }
 
@@ -813,6 +918,10 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     return DM_E_ARG;
   }
   const bool have_spec = c->scans[0].L.tspec != 0;
+  if (t.multipass && c->bf16x3()) {
+    c->err = "the BF16x3 form has its own transform path (multipass must be 0)";
+    return DM_E_ARG;
+  }
   if (t.multipass && !have_spec) {
     c->err = "the three-kernel path needs DM_FLAG_MULTIPASS at init";
     return DM_E_ARG;
@@ -1105,7 +1214,7 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   std::vector<dm_tuning> cand;
   const int chunk_opts[3] = {std::max(1, base.probe_chunks / 2), base.probe_chunks,
                              std::min(DM_MAX_PROBE_CHUNKS, base.probe_chunks * 2)};
-  const bool have_spec = c->scans[0].L.tspec != 0;
+  const bool have_spec = c->scans[0].L.tspec != 0 && !c->bf16x3();
   for (int mp = 0; mp <= 1; ++mp) {
     if (mp == 1 && !have_spec) continue;
     if (mp == 0 && c->F > 128) continue;

@@ -732,17 +732,18 @@ __global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scan
   const int col = t % T, row0 = t / T;
   const int cx = tx * T + col;
   const int ry = ty * T + row0;
+  // the normaliser sum_j sum_k |P_k|^2 accumulates in double
   float2 num[PPT];
-  float den[PPT];
+  double den[PPT];
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) { num[q] = make_float2(0.f, 0.f); den[q] = 0.f; }
+  for (int q = 0; q < PPT; ++q) { num[q] = make_float2(0.f, 0.f); den[q] = 0.0; }
   const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   const size_t FF = (size_t)F * F;
   constexpr int U = 4;
   int e = e0;
   for (; e + U <= e1; e += U) {
     float2 vv[U][PPT];
-    float dd[U][PPT];
+    float dd[U][PPT];  // added to den in double below
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int jv = tile_views[e + k];
@@ -760,7 +761,10 @@ __global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scan
 #pragma unroll
     for (int k = 0; k < U; ++k)
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) { num[q] = cadd(num[q], vv[k][q]); den[q] += dd[k][q]; }
+      for (int q = 0; q < PPT; ++q) {
+        num[q] = cadd(num[q], vv[k][q]);
+        den[q] += (double)dd[k][q];
+      }
   }
   for (; e < e1; ++e) {
     const int jv = tile_views[e];
@@ -772,7 +776,7 @@ __global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scan
       const int u = ry + RSTEP * q - yj;
       if (((unsigned)v < (unsigned)F) && ((unsigned)u < (unsigned)F)) {
         num[q] = cadd(num[q], oj[(size_t)u * F + v]);
-        den[q] += D[u * F + v];
+        den[q] += (double)D[u * F + v];
       }
     }
   }
@@ -780,8 +784,8 @@ __global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scan
 #pragma unroll
   for (int q = 0; q < PPT; ++q) {
     const int r = ry + RSTEP * q;
-    if (r < H && cx < W && den[q] > 0.f) {
-      const float inv = 1.0f / den[q];
+    if (r < H && cx < W && den[q] > 0.0) {
+      const float inv = (float)(1.0 / den[q]);
       const float2 on = make_float2(num[q].x * inv, num[q].y * inv);
       const float2 oo = O[(size_t)r * W + cx];
       e_d += cabs2(csub(on, oo));

@@ -58,6 +58,10 @@ def test_workspace_bytes_valid_and_invalid():
     # F = 256 needs the multi-pass spectrum buffer as well
     d256 = desc(frame=256, obj_h=300, obj_w=300)
     assert dm.dm_workspace_bytes(d256) > 2 * 10 * 2 * 256 * 256 * 8
+    # so does the BF16x3 form, plus its 128 KB split DFT matrix
+    f32 = desc(frame=128, obj_h=200, obj_w=200)
+    b16 = desc(frame=128, obj_h=200, obj_w=200, precision=dm.DM_BF16X3_DFT)
+    assert dm.dm_workspace_bytes(b16) >= dm.dm_workspace_bytes(f32) + 10 * 2 * 128 * 128 * 8
 
 
 def _init_status(d, pos, ws_bytes=None, ptrs=(256, 256, 256, 256)):
@@ -93,6 +97,8 @@ def test_init_rejects_small_workspace_and_bad_pointers():
     assert _init_status(desc(beta=2.0), pos)[0] == dm.DM_E_ARG
     assert _init_status(desc(precision=dm.DM_BF16X3_DFT, frame=64), pos)[0] \
         == dm.DM_E_UNSUPPORTED
+    big = desc(precision=dm.DM_BF16X3_DFT, frame=128, obj_h=200, obj_w=200, n_modes=9)
+    assert _init_status(big, pos)[0] == dm.DM_E_UNSUPPORTED
 
 
 def test_calls_on_null_context():

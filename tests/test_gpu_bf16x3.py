@@ -1,0 +1,116 @@
+"""GPU parity of the BF16x3 precision form (2-D DFT as split-bfloat16 matrix
+products on the matrix cores, F = 128).
+
+Two references per case: the CPU emulation of the same split products
+(oracle.bf16x3_oracle), which the GPU must match to 1e-6 relative L2 (the
+GPU accumulates in float32 where the emulation sums exactly), and the FP64
+oracle, against which the error of the form is measured and printed; it is
+bounded here by 1e-4, the three-term split's error level."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import bf16x3_oracle as b3
+from oracle import dm_oracle as oracle
+from paper_1808_10375_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EMU_TOL = 1e-6
+FP64_TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b, w=None):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    if w is None:
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    return float(np.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2)))
+
+
+def gpu_steps(case, n_iter=1, precision=None):
+    import torch
+    from paper_1808_10375_amd import dm
+    if precision is None:
+        precision = dm.DM_BF16X3_DFT
+    dev = torch.device("cuda:0")
+    I = torch.from_numpy(np.ascontiguousarray(case["I"], dtype=np.float32)).to(dev)
+    P = torch.from_numpy(np.ascontiguousarray(case["P"], dtype=np.complex64)).to(dev)
+    O = torch.from_numpy(np.ascontiguousarray(case["O"], dtype=np.complex64)).to(dev)
+    ctx = dm.DMContext(I, case["pos"], P, O, beta=case["beta"], precision=precision)
+    psi = torch.from_numpy(np.ascontiguousarray(case["psi"], dtype=np.complex64)).to(dev)
+    ctx.set_state(psi, P, O, 0)
+    ctx.iterate(n_iter)
+    e = ctx.errors()
+    psi2, P2, O2, it = ctx.state()
+    out = (psi2.cpu().numpy(), P2.cpu().numpy(), O2.cpu().numpy(), e, it)
+    ctx.free()
+    return out
+
+
+def compare(case):
+    args = (case["psi"].astype(np.complex128), case["P"].astype(np.complex128),
+            case["O"].astype(np.complex128), case["pos"], case["I"].astype(np.float64),
+            case["beta"])
+    psi_e, P_e, O_e = b3.iterate(*args)
+    psi_x, P_x, O_x, e_x = oracle.iterate(*args)
+    den = oracle.object_update(psi_x, args[1], args[2], case["pos"])[1]
+    psi_g, P_g, O_g, e_g, it = gpu_steps(case)
+    assert it == 1
+    emu = (rel(psi_g, psi_e), rel(O_g, O_e, den), rel(P_g, P_e))
+    f64 = (rel(psi_g, psi_x), rel(O_g, O_x, den), rel(P_g, P_x))
+    say(f"  vs emulation: psi {emu[0]:.2e} O(w) {emu[1]:.2e} P {emu[2]:.2e} | "
+        f"vs FP64: psi {f64[0]:.2e} O(w) {f64[1]:.2e} P {f64[2]:.2e} | "
+        f"eps_P gpu {e_g['eps_probe']:.6e} fp64 {e_x['eps_probe']:.6e}")
+    assert max(emu) <= EMU_TOL, emu
+    assert max(f64) <= FP64_TOL, f64
+    return emu, f64
+
+
+@pytest.mark.parametrize("seed,n,m,h,w,perturb", [(31, 7, 3, 200, 190, 0.3),
+                                                  (32, 5, 1, 128, 160, None),
+                                                  (33, 4, 8, 170, 170, 0.5),
+                                                  (34, 9, 5, 260, 240, 0.3)])
+def test_bf16x3_one_step(seed, n, m, h, w, perturb):
+    say(f"case bf16x3 seed={seed} N={n} F=128 M={m} obj={h}x{w} perturb={perturb}")
+    compare(synth.random_case(seed, n, 128, m, h, w, perturb=perturb))
+
+
+def test_bf16x3_multimode_scan_subset_one_step():
+    """300 views of the 5-mode 128x128 spiral scan after 5 FP64 iterations."""
+    s = synth.multimode_spiral_128(1, n_frames=300)
+    psi = oracle.init_views(s.P0, s.O0, s.pos)
+    P, O = s.P0.astype(np.complex128), s.O0.astype(np.complex128)
+    for _ in range(5):
+        psi, P, O, _ = oracle.iterate(psi, P, O, s.pos, s.I.astype(np.float64), 0.8)
+    say("case bf16x3 spiral subset 300 x 5 x 128^2 after 5 iterations")
+    compare(dict(psi=psi.astype(np.complex64), P=P.astype(np.complex64),
+                 O=O.astype(np.complex64), I=s.I, pos=s.pos, beta=0.8))
+
+
+def test_bf16x3_error_history_tracks_fp32_path():
+    """30 iterations of the 300-view spiral subset: the BF16x3 form's eps_P
+    follows the FP32 path's within a few percent."""
+    import torch
+    from paper_1808_10375_amd import dm
+    s = synth.multimode_spiral_128(1, n_frames=300)
+    dev = torch.device("cuda:0")
+    hist = {}
+    for name, prec in (("fp32", dm.DM_FP32_FFT), ("bf16x3", dm.DM_BF16X3_DFT)):
+        ctx = dm.DMContext(torch.from_numpy(s.I).to(dev), s.pos,
+                           torch.from_numpy(s.P0).to(dev), torch.from_numpy(s.O0).to(dev),
+                           precision=prec)
+        ctx.iterate(30)
+        hist[name] = np.array([e["eps_probe"] for e in ctx.error_history()])
+        ctx.free()
+    dev_rel = np.abs(hist["bf16x3"] - hist["fp32"]) / hist["fp32"]
+    say(f"  eps_P at 30: fp32 {hist['fp32'][-1]:.4e} bf16x3 {hist['bf16x3'][-1]:.4e}; "
+        f"max rel deviation {dev_rel.max():.2e}")
+    assert np.all(np.isfinite(hist["bf16x3"]))
+    assert dev_rel[-1] <= 0.05 and np.median(dev_rel) <= 0.05

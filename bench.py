@@ -158,6 +158,52 @@ def bench_batched(steps: int, warmup: int, conv_iters: int):
                                     "max": max(final)}}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_bf16x3(scan, steps: int, warmup: int, conv_iters: int, fp32_err):
+    """The same scan through the BF16x3 form (each 2-D DFT as split-bfloat16
+    complex matrix products on MFMA); 96 F^3 flops per frame-mode."""
+    import torch
+    from paper_1808_10375_amd import dm
+    dev = torch.device("cuda:0")
+    n, f, m = scan.n_frames, scan.frame, scan.n_modes
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        ctx = dm.DMContext(torch.from_numpy(scan.I).to(dev), scan.pos,
+                           torch.from_numpy(scan.P0).to(dev), torch.from_numpy(scan.O0).to(dev),
+                           beta=scan.beta, precision=dm.DM_BF16X3_DFT,
+                           flags=dm.DM_FLAG_PHASE_TIMING, stream=stream)
+        ctx.iterate(warmup)
+        ctx.phase_times()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ctx.iterate(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        phases, n_timed = ctx.phase_times()
+        done = warmup + steps
+        if conv_iters > done:
+            ctx.iterate(conv_iters - done)
+        hist = ctx.error_history(1, max(conv_iters, done))
+        ctx.free()
+    views_ms = phases["views"] / max(n_timed, 1)
+    flops = 96.0 * f ** 3 * n * m
+    errs = [e["eps_probe"] for e in hist]
+    return {"workload": "the same scan as the headline line",
+            "value": n * m / (elapsed / steps), "unit": "frame·mode/s",
+            "ms_per_step": 1e3 * elapsed / steps, "views_ms": views_ms,
+            "roofline": {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
+                         "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (views_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                         "kernel": "views (k_mf_rows_fwd, k_mf_cols, k_mf_rows_inv)",
+                         "alg_flops_per_launch": flops},
+            "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
+            "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
+            "final_err_vs_fp32": {"bf16x3": errs[-1], "fp32": fp32_err}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched-scans (and other forms') measurements")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
+                    help="transform form of the headline run (bf16x3: F = 128 only)")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -213,7 +261,9 @@ def main():
         P0 = torch.from_numpy(scan.P0).to(dev)
         O0 = torch.from_numpy(scan.O0).to(dev)
         flags = dm.DM_FLAG_PHASE_TIMING | (dm.DM_FLAG_MULTIPASS if args.multipass else 0)
-        ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream)
+        prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
+        ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream,
+                           precision=prec)
         ctx.iterate(args.warmup)
         ctx.phase_times()  # drop the warm-up marks (synchronises)
         torch.cuda.synchronize()
@@ -254,7 +304,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n_frames": n, "n_modes": m, "frame": f,
                    "object": [h, w], "beta": scan.beta,
-                   "precision": "fp32-fft" + ("-multipass" if args.multipass else "")},
+                   "precision": (args.precision + ("-fft" if args.precision == "fp32" else "-dft")
+                                 + ("-multipass" if args.multipass else ""))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
@@ -267,8 +318,18 @@ def main():
         "iters_to_err_1e-3": reach,
         "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
     }
-    if not args.no_forms and args.config == 1:
-        out["forms"] = {"batched": bench_batched(args.steps, args.warmup, args.conv_iters)}
+    if args.precision == "bf16x3":
+        flops = 96.0 * f ** 3 * n * m
+        out["roofline"] = {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
+                           "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": flops / (views_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                           "traffic": None, "kernel": "views (3 MFMA kernels)",
+                           "alg_flops_per_launch": flops, "avg_launch_ms": views_ms}
+        out["dtype"] = "bf16x3/f32"
+    if not args.no_forms and args.config == 1 and args.precision == "fp32":
+        out["forms"] = {"batched": bench_batched(args.steps, args.warmup, args.conv_iters),
+                        "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,
+                                               errs[-1])}
     if not args.no_cpu:
         print("# timing the FP64 oracle on a sample of the scan", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, min(args.cpu_sample, n))

@@ -59,6 +59,11 @@ def main():
     ap.add_argument("--traffic")
     ap.add_argument("--command", default="")
     ap.add_argument("--title", default="")
+    ap.add_argument("--mfma", help="counter CSV with SQ_VALU_MFMA_BUSY_CYCLES, "
+                    "GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_BF16")
+    ap.add_argument("--simds", type=int, default=1024, help="SIMDs on the device")
+    ap.add_argument("--xcds", type=int, default=8,
+                    help="GRBM_GUI_ACTIVE instances summed in the CSV (one per XCD)")
     args = ap.parse_args()
 
     rows = list(csv.DictReader(open(args.stats)))
@@ -90,6 +95,23 @@ def main():
         if vk:
             traffic = {"read": fetch[vk] * 1024 * ff, "written": write[vk] * 1024 * fw}
             traffic["total"] = traffic["read"] + traffic["written"]
+    if args.mfma:
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(args.mfma)):
+            per[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        lines += ["", "Matrix-core counters per dispatch (MFMA busy = "
+                  "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x "
+                  f"{args.simds} SIMDs); flops = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512):", "",
+                  "| kernel | MFMA busy % | bf16 MFMA GFLOP | GPU cycles |",
+                  "|---|---:|---:|---:|"]
+        for k, d in per.items():
+            m = {c: sum(v) / len(v) for c, v in d.items()}
+            if m.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0) <= 0:
+                continue
+            cyc = m["GRBM_GUI_ACTIVE"] / args.xcds
+            util = 100.0 * m["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * args.simds)
+            lines.append(f"| `{k}` | {util:.1f} | "
+                         f"{m['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512 / 1e9:.1f} | {cyc:.3g} |")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")

@@ -107,14 +107,16 @@ def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
 # training
 # ---------------------------------------------------------------------------
 def train(net, x, t, x_val, t_val, epochs: int, batch: int, seed: int = 0,
-          log_every: int = 200):
-    """Adam over shuffled minibatches; returns the history of losses."""
+          log_every: int = 50, max_seconds: float = 1e30):
+    """Adam over shuffled minibatches; returns the history of losses.  Stops
+    early, at the end of a step, once `max_seconds` have passed."""
     import torch
     gen = torch.Generator(device="cpu").manual_seed(seed)
     n = x.shape[0]
     hist = []
     step = 0
     t_start = time.time()
+    stopped = False
     for ep in range(epochs):
         perm = torch.randperm(n, generator=gen).to(x.device)
         for b0 in range(0, n - batch + 1, batch):
@@ -126,9 +128,15 @@ def train(net, x, t, x_val, t_val, epochs: int, batch: int, seed: int = 0,
                 log(f"train step {step} epoch {ep} loss {loss:.5f} "
                     f"({time.time() - t_start:.0f} s)")
             step += 1
+            if time.time() - t_start > max_seconds:
+                stopped = True
+                break
         vl = validation_loss(net, x_val, t_val, batch)
         hist.append({"step": step, "epoch": ep, "val_loss": vl})
         log(f"epoch {ep}: validation loss {vl:.5f}")
+        if stopped:
+            log(f"training stopped by the time limit after {step} steps")
+            break
     return hist, step, time.time() - t_start
 
 
@@ -277,6 +285,7 @@ def main(argv=None):
     ap.add_argument("--out", type=str, default="")
     ap.add_argument("--save-params", type=str, default="")
     ap.add_argument("--load-params", type=str, default="")
+    ap.add_argument("--max-train-s", type=float, default=600.0)
     a = ap.parse_args(argv)
     import torch
     from .dmnet import DMNet
@@ -299,7 +308,8 @@ def main(argv=None):
         t_pairs = time.time() - t0
         log(f"pairs: {x.shape[0]} training, {xv.shape[0]} validation ({t_pairs:.0f} s)")
         v0 = validation_loss(net, xv, tv, a.batch)
-        hist, steps, t_train = train(net, x, t, xv, tv, a.epochs, a.batch)
+        hist, steps, t_train = train(net, x, t, xv, tv, a.epochs, a.batch,
+                                     max_seconds=a.max_train_s)
         report["training"] = {
             "scans": a.train_scans, "frames_per_scan": a.train_frames,
             "object": a.train_obj, "dm_iters": a.dm_iters, "pairs": int(x.shape[0]),

@@ -2,10 +2,15 @@
 products on the matrix cores, F = 128).
 
 Two references per case: the CPU emulation of the same split products
-(oracle.bf16x3_oracle), which the GPU must match to 1e-6 relative L2 (the
-GPU accumulates in float32 where the emulation sums exactly), and the FP64
-oracle, against which the error of the form is measured and printed; it is
-bounded here by 1e-4, the three-term split's error level."""
+(oracle.bf16x3_oracle) and the FP64 oracle.  The emulation sums each
+matrix product exactly; the matrix cores do not: a gfx950 probe of
+v_mfma_f32_16x16x32_bf16 shows terms lying more than about 2^-24 below the
+largest term of one instruction's dot product (accumulator included) being
+dropped, so the GPU departs from the exact-sum emulation by a few 1e-6 over
+the four transform passes.  The bar against the emulation is therefore
+1e-5, which still fails any mistake in the split itself (a missing hi*lo or
+lo*hi term costs about 2^-9); the error of the form against FP64 is printed
+for every case and bounded by 1e-4."""
 import sys
 
 import numpy as np
@@ -17,7 +22,7 @@ from paper_1808_10375_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-EMU_TOL = 1e-6
+EMU_TOL = 1e-5
 FP64_TOL = 1e-4
 
 
@@ -60,6 +65,7 @@ def compare(case):
             case["beta"])
     psi_e, P_e, O_e = b3.iterate(*args)
     psi_x, P_x, O_x, e_x = oracle.iterate(*args)
+    say(f"  emulation vs FP64: psi {rel(psi_e, psi_x):.2e} P {rel(P_e, P_x):.2e}")
     den = oracle.object_update(psi_x, args[1], args[2], case["pos"])[1]
     psi_g, P_g, O_g, e_g, it = gpu_steps(case)
     assert it == 1

@@ -218,6 +218,8 @@ def main():
                     help="skip the batched-scans (and other forms') measurements")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="transform form of the headline run (bf16x3: F = 128 only)")
+    ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="override the library's default view kernel (dm_tuning.view_path)")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -264,6 +266,10 @@ def main():
         prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
         ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream,
                            precision=prec)
+        if args.view_path is not None:
+            tune = ctx.tuning()
+            ctx.set_tuning(tune["obj_tile"], tune["probe_chunks"], args.view_path)
+        view_path = ctx.tuning()["view_path"]
         ctx.iterate(args.warmup)
         ctx.phase_times()  # drop the warm-up marks (synchronises)
         torch.cuda.synchronize()
@@ -309,8 +315,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": ("k_fourier_fused<%d>" % f) if (f <= 128 and not args.multipass)
-                     else "views (3 kernels)",
+                     "kernel": {0: "k_fourier_fused<%d>" % f, 1: "views (3 kernels)",
+                                2: "k_fourier_stream<%d>" % f,
+                                3: "k_fourier_stream<%d> (cached psi)" % f}[view_path],
                      "alg_bytes_per_launch": alg, "avg_launch_ms": views_ms},
         "step_roofline_frac": step_alg_bytes(n, m, f) / (ms_per_step * 1e-3) / 1e9
         / HBM_PEAK_GBS,

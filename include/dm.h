@@ -122,6 +122,17 @@ typedef struct {
 #define DM_MAX_MODES 16
 #define DM_MAX_PROBE_CHUNKS 64
 
+/* dm_tuning.view_path values */
+#define DM_VIEWS_FUSED 0           /* one workgroup per view, transforms
+                                      recomputed instead of stored (F <= 128) */
+#define DM_VIEWS_THREE_KERNEL 1    /* rows / columns / rows through the
+                                      spectrum buffer                        */
+#define DM_VIEWS_STREAMED 2        /* persistent workgroups, spectra in a
+                                      per-workgroup scratch slot, psi loaded
+                                      and stored with the non-temporal hint
+                                      (F <= 128)                             */
+#define DM_VIEWS_STREAMED_CACHED 3 /* the same with ordinary psi accesses    */
+
 /* Launch shapes chosen per context (dm_set_tuning / dm_autotune).  They
  * change the speed of an iteration and the summation order of the probe
  * sums (results agree to rounding), nothing else. */
@@ -131,9 +142,13 @@ typedef struct {
   int32_t probe_chunks;  /* runs of views summed separately in the Eq. 4
                             partial sums, 1..DM_MAX_PROBE_CHUNKS (capped at
                             each scan's view count)                       */
-  int32_t multipass;     /* 1: three-kernel transform path; only where the
-                            workspace holds its spectrum buffer (F = 256 or
-                            DM_FLAG_MULTIPASS at init); forced for F = 256 */
+  int32_t view_path;     /* transform path of the view update (Eq. 3):
+                            DM_VIEWS_FUSED, DM_VIEWS_THREE_KERNEL (only
+                            where the workspace holds its spectrum buffer:
+                            F = 256 or DM_FLAG_MULTIPASS at init; forced for
+                            F = 256), DM_VIEWS_STREAMED or
+                            DM_VIEWS_STREAMED_CACHED (F <= 128); ignored by
+                            the BF16x3 form, which must be given 0        */
   int32_t reserved;      /* must be 0                                     */
 } dm_tuning;
 

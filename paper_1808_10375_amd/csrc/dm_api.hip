@@ -49,7 +49,8 @@ dm_tuning default_tuning(const dm_desc& d) {
   dm_tuning t{};
   t.obj_tile = 16;
   t.probe_chunks = default_chunks(d.frame);
-  t.multipass = (has_spectrum_buffer(d) && !is_bf16x3(d)) ? 1 : 0;
+  t.view_path = (has_spectrum_buffer(d) && !is_bf16x3(d)) ? DM_VIEWS_THREE_KERNEL
+                                                              : DM_VIEWS_FUSED;
   return t;
 }
 
@@ -121,8 +122,18 @@ ScanLayout scan_layout(const dm_desc& d) {
   return L;
 }
 
+// persistent workgroups of the streamed view path: one per compute unit of
+// an MI355X, fewer when the batch has fewer views
+constexpr int kStreamSlots = 256;
+
+int stream_slots(int n_scans, const dm_desc* d) {
+  size_t views = 0;
+  for (int s = 0; s < n_scans; ++s) views += d[s].n_frames;
+  return (int)std::min<size_t>(views, kStreamSlots);
+}
+
 struct CtxLayout {
-  size_t scans, vmap, tmap, cmap, tw, wf, flags, header;
+  size_t scans, vmap, tmap, cmap, tw, wf, vscr, flags, header;
   std::vector<size_t> scan_base;
   std::vector<ScanLayout> sl;
   size_t total;
@@ -147,6 +158,12 @@ CtxLayout ctx_layout(int n_scans, const dm_desc* d) {
   C.cmap = take(sizeof(int2) * (size_t)DM_MAX_PROBE_CHUNKS * n_scans);
   C.tw = take(sizeof(float2) * d[0].frame);
   C.wf = is_bf16x3(d[0]) ? take(sizeof(uint4) * dmk::kMfWords) : 0;
+  // spectra of the view in hand, per persistent workgroup of the streamed
+  // path: [slot][M][F][F] complex64
+  C.vscr = (!is_bf16x3(d[0]) && d[0].frame <= 128)
+               ? take((size_t)stream_slots(n_scans, d) * d[0].n_modes * d[0].frame *
+                      d[0].frame * 8)
+               : 0;
   C.flags = take(sizeof(int));
   C.header = off;
   for (int s = 0; s < n_scans; ++s) {
@@ -243,6 +260,7 @@ struct dm_ctx {
   std::string err;
   int iters = 0;
   int total_views = 0, total_tiles = 0, total_chunks = 0;
+  int stream_slots = 0;
   dm_tuning tune{};
   // graph of one iteration
   hipGraph_t graph = nullptr;
@@ -269,6 +287,7 @@ struct dm_ctx {
   int2* tmap() { return at<int2>(CL.tmap); }
   int2* cmap() { return at<int2>(CL.cmap); }
   float2* tw() { return at<float2>(CL.tw); }
+  float2* vscr() { return at<float2>(CL.vscr); }
   const uint4* wf() { return at<uint4>(CL.wf); }
   bool bf16x3() const { return is_bf16x3(scans[0].d); }
   int* flags_dev() { return at<int>(CL.flags); }
@@ -431,7 +450,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
     v.C = S.C;
     v.chunk = S.chunk;
     v.n_psi_parts = is_bf16x3(S.d)  ? 2 * S.d.n_frames
-                    : t.multipass   ? L.n_psi_parts_multi
+                    : t.view_path == DM_VIEWS_THREE_KERNEL ? L.n_psi_parts_multi
                                     : L.n_psi_parts_fused;
     v.beta = S.d.beta;
     v.pad = 0;
@@ -446,7 +465,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
                            hipMemcpyHostToDevice, c->stream));
   DM_HIP(c, hipMemcpyAsync(c->cmap(), cmap.data(), cmap.size() * sizeof(int2),
                            hipMemcpyHostToDevice, c->stream));
-  if (t.multipass) {
+  if (t.view_path == DM_VIEWS_THREE_KERNEL) {
     const int lds =
         (int)((size_t)cols_per_block(c->F, c->M) * c->M * (c->F + 1) * sizeof(float2));
     DM_HIP(c, set_cols_lds(c->F, lds));
@@ -600,9 +619,34 @@ dm_status launch_views_mfma(dm_ctx* c) {
   return DM_OK;
 }
 
+template <int F>
+dm_status launch_views_streamed(dm_ctx* c, bool nt) {
+  const int grid = std::min(c->total_views, c->stream_slots);
+  if (nt)
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true>), dim3(grid), dim3(F * F / 16), 0,
+                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+                       c->vscr());
+  else
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, false>), dim3(grid), dim3(F * F / 16), 0,
+                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+                       c->vscr());
+  DM_LAUNCHED(c, "k_fourier_stream");
+  return DM_OK;
+}
+
 dm_status launch_views(dm_ctx* c) {
   if (c->bf16x3()) return launch_views_mfma(c);
-  if (!c->tune.multipass) {
+  const int vp = c->tune.view_path;
+  if (vp == DM_VIEWS_STREAMED || vp == DM_VIEWS_STREAMED_CACHED) {
+    const bool nt = vp == DM_VIEWS_STREAMED;
+    switch (c->F) {
+      case 16: return launch_views_streamed<16>(c, nt);
+      case 32: return launch_views_streamed<32>(c, nt);
+      case 64: return launch_views_streamed<64>(c, nt);
+      case 128: return launch_views_streamed<128>(c, nt);
+    }
+  }
+  if (vp == DM_VIEWS_FUSED) {
     switch (c->F) {
       case 16: return launch_views_fused<16>(c);
       case 32: return launch_views_fused<32>(c);
@@ -772,6 +816,7 @@ dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const floa
     c->scans.push_back(std::move(S));
   }
   c->total_views = (int)vmap.size();
+  c->stream_slots = stream_slots(n_scans, descs);
   auto bail = [&](dm_status e) {
     g_init_error = c->err;
     delete c;
@@ -880,12 +925,12 @@ bool cache_lookup(const char* path, const std::string& key, dm_tuning* t) {
     int tile, chunks, multi;
     if (sscanf(line,
                "{\"key\": \"%255[^\"]\", \"obj_tile\": %d, \"probe_chunks\": %d, "
-               "\"multipass\": %d",
+               "\"view_path\": %d",
                k, &tile, &chunks, &multi) == 4 &&
         key == k) {
       t->obj_tile = tile;
       t->probe_chunks = chunks;
-      t->multipass = multi;
+      t->view_path = multi;
       t->reserved = 0;
       found = true;  // the last entry for a key wins
     }
@@ -898,9 +943,9 @@ void cache_store(const char* path, const std::string& key, const dm_tuning& t, d
   FILE* f = fopen(path, "a");
   if (!f) return;
   fprintf(f,
-          "{\"key\": \"%s\", \"obj_tile\": %d, \"probe_chunks\": %d, \"multipass\": %d, "
+          "{\"key\": \"%s\", \"obj_tile\": %d, \"probe_chunks\": %d, \"view_path\": %d, "
           "\"ms_per_iter\": %.6f}\n",
-          key.c_str(), t.obj_tile, t.probe_chunks, t.multipass, ms);
+          key.c_str(), t.obj_tile, t.probe_chunks, t.view_path, ms);
   fclose(f);
 }
 
@@ -913,20 +958,20 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     c->err = "probe_chunks out of range";
     return DM_E_ARG;
   }
-  if (t.reserved != 0 || (t.multipass != 0 && t.multipass != 1)) {
+  if (t.reserved != 0 || t.view_path < DM_VIEWS_FUSED || t.view_path > DM_VIEWS_STREAMED_CACHED) {
     c->err = "bad tuning fields";
     return DM_E_ARG;
   }
   const bool have_spec = c->scans[0].L.tspec != 0;
-  if (t.multipass && c->bf16x3()) {
-    c->err = "the BF16x3 form has its own transform path (multipass must be 0)";
+  if (t.view_path != DM_VIEWS_FUSED && c->bf16x3()) {
+    c->err = "the BF16x3 form has its own transform path (view_path must be 0)";
     return DM_E_ARG;
   }
-  if (t.multipass && !have_spec) {
+  if (t.view_path == DM_VIEWS_THREE_KERNEL && !have_spec) {
     c->err = "the three-kernel path needs DM_FLAG_MULTIPASS at init";
     return DM_E_ARG;
   }
-  if (!t.multipass && c->F > 128) {
+  if (t.view_path != DM_VIEWS_THREE_KERNEL && c->F > 128) {
     c->err = "F = 256 only has the three-kernel path";
     return DM_E_ARG;
   }
@@ -1215,16 +1260,17 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   const int chunk_opts[3] = {std::max(1, base.probe_chunks / 2), base.probe_chunks,
                              std::min(DM_MAX_PROBE_CHUNKS, base.probe_chunks * 2)};
   const bool have_spec = c->scans[0].L.tspec != 0 && !c->bf16x3();
-  for (int mp = 0; mp <= 1; ++mp) {
-    if (mp == 1 && !have_spec) continue;
-    if (mp == 0 && c->F > 128) continue;
+  for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_CACHED; ++mp) {
+    if (c->bf16x3() && mp != DM_VIEWS_FUSED) continue;
+    if (mp == DM_VIEWS_THREE_KERNEL && !have_spec) continue;
+    if (mp != DM_VIEWS_THREE_KERNEL && c->F > 128) continue;
     for (int tile : {16, 32})
       for (int ch : chunk_opts) {
         dm_tuning t{tile, ch, mp, 0};
         bool dup = false;
         for (auto& u : cand)
           if (u.obj_tile == t.obj_tile && u.probe_chunks == t.probe_chunks &&
-              u.multipass == t.multipass)
+              u.view_path == t.view_path)
             dup = true;
         if (!dup) cand.push_back(t);
       }

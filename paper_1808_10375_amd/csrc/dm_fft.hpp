@@ -172,6 +172,16 @@ __device__ __forceinline__ void bstore2(rsrc_t r, float2 x, int voff, int soff) 
   u32x2 v = {__float_as_uint(x.x), __float_as_uint(x.y)};
   __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
 }
+// the same with the non-temporal cache hint (streamed data that should not
+// displace the probe and object from L2)
+__device__ __forceinline__ float2 bload2_nt(rsrc_t r, int voff, int soff) {
+  u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2);
+  return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+__device__ __forceinline__ void bstore2_nt(rsrc_t r, float2 x, int voff, int soff) {
+  u32x2 v = {__float_as_uint(x.x), __float_as_uint(x.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
+}
 
 // Index that is the same for every lane of a wave when F >= 64 (a wave's 64
 // lanes then share t / F); keeping it in an SGPR makes its table loads scalar.

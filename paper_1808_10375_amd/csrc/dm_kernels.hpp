@@ -321,6 +321,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
 
   const int t = threadIdx.x;
   for (int i = t; i < F; i += NT) twl[i] = tw[i];
+  __syncthreads();  // the twiddles are read by every wave
   const int2 vm = vmap[xcd_slot(blockIdx.x, total)];
   const ScanDev& sc = scans[vm.x];
   const int j = vm.y;
@@ -473,6 +474,147 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
   if (t == 0) {
     err_psi[2 * j] = e_d;
     err_psi[2 * j + 1] = e_n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streamed view update (F <= 128): a persistent grid of one workgroup per
+// compute unit; workgroup b owns a slot of scratch (the spectra of every
+// mode of the view in hand, thread-major so each thread reads back exactly
+// what it wrote) and walks views b, b + G, ... of the XCD-interleaved order.
+//   pass 1  per mode: Z = 2 P O - psi, forward DFT, mode sum S += |Z~|^2,
+//           Z~ -> scratch
+//   scale   g = sqrt(I / S) / F^2 (definition of F_c), kept in registers
+//   pass 2  per mode: Z~ from scratch, times g, inverse DFT, Z' -> scratch
+//   pass 3  per mode: Z' from scratch, psi' = psi + beta (Z' - P O)
+//           (Eq. 3), object numerator sum_k conj(P_k) psi'_k in registers
+// Every mode is transformed twice (no recomputation), no transform runs
+// while the object numerator is live, and psi is read twice and written
+// once with the non-temporal hint (NT) so the probe and the object stay in
+// L2; the slot's scratch is rewritten view after view and stays in cache.
+// ---------------------------------------------------------------------------
+template <int F, bool NT_HINT>
+__global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
+    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
+    const float2* __restrict__ tw, int M, float2* __restrict__ vscr) {
+  constexpr int B = F / 16;
+  constexpr int NT = F * B;
+  constexpr int LD = F + 1;
+  constexpr int FF = F * F;
+  __shared__ float2 buf[F * LD];
+  __shared__ float red[2 * ((NT + 63) / 64)];
+  __shared__ float2 twl[F];
+
+  const int t = threadIdx.x;
+  for (int i = t; i < F; i += NT) twl[i] = tw[i];
+  __syncthreads();
+  const int c = t % F;
+  const int g0 = wave_uniform_div<F>(t);
+  const rsrc_t rs = make_rsrc(vscr + (size_t)blockIdx.x * M * FF, (uint32_t)(M * FF * 8));
+  const int vS = t * 8;  // scratch: [mode][r][thread]
+  auto rowS = [&](int m, int r) { return (m * 16 + r) * NT * 8; };
+
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int2 vm = vmap[xcd_slot(item, total)];
+    const ScanDev& sc = scans[vm.x];
+    const int j = vm.y;
+    const int H = sc.H, W = sc.W;
+    const float beta = sc.beta;
+    const int y0 = sc.pos[2 * j], x0 = sc.pos[2 * j + 1];
+    const rsrc_t rpsi = make_rsrc(sc.psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
+    const rsrc_t rP = make_rsrc(sc.P, (uint32_t)(M * FF * 8));
+    const rsrc_t rO = make_rsrc(sc.O, (uint32_t)((size_t)H * W * 8));
+    const int vF = (g0 * F + c) * 8;
+    const int vO = (g0 * W + c) * 8;
+    const int sO = (y0 * W + x0) * 8;
+    auto rowF = [&](int u1) { return B * u1 * F * 8; };
+    auto rowO = [&](int u1) { return B * u1 * W * 8; };
+    auto ld_psi = [&](int off) { return NT_HINT ? bload2_nt(rpsi, vF, off) : bload2(rpsi, vF, off); };
+
+    float2 a[1][16];
+    float S[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[r] = 0.f;
+    // ---- pass 1
+    for (int m = 0; m < M; ++m) {
+      const int sm = m * FF * 8;
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) {
+        const float2 ps = ld_psi(sm + rowF(u1));
+        const float2 phi = cmul(bload2(rP, vF, sm + rowF(u1)), bload2(rO, vO, sO + rowO(u1)));
+        a[0][u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      Frame2D<F, -1, 1>::fwd(a, buf, twl, c, g0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        S[r] += cabs2(a[0][r]);
+        bstore2(rs, a[0][r], vS, rowS(m, r));
+      }
+    }
+    // ---- modulus scale from I staged through LDS (padded rows)
+    {
+      float* bI = reinterpret_cast<float*>(buf);
+      const float* __restrict__ Ij = sc.I + (size_t)j * FF;
+      __syncthreads();
+      for (int e = t; e < FF; e += NT) bI[(e / F) * (F + 1) + (e % F)] = Ij[e];
+      __syncthreads();
+      const float inv_ff = 1.0f / (float)FF;
+#pragma unroll
+      for (int i = 0; i < 16 / B; ++i)
+#pragma unroll
+        for (int l2 = 0; l2 < B; ++l2) {
+          const int r = i * B + l2;
+          const int l = (g0 + B * i) + 16 * l2;
+          const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
+          const float sv = S[r];
+          S[r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+        }
+      __syncthreads();  // bI aliases the exchange buffer
+    }
+    // ---- pass 2: scaled spectra back to the spatial domain
+    for (int m = 0; m < M; ++m) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a[0][r] = cscale(bload2(rs, vS, rowS(m, r)), S[r]);
+      Frame2D<F, 1, 1>::inv(a, buf, twl, c, g0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bstore2(rs, a[0][r], vS, rowS(m, r));
+    }
+    // ---- pass 3: view update and the object numerator
+    float2 oacc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
+    float e_d = 0.f, e_n = 0.f;
+    for (int m = 0; m < M; ++m) {
+      const int sm = m * FF * 8;
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) {
+        const float2 zp = bload2(rs, vS, rowS(m, u1));
+        const float2 pr = bload2(rP, vF, sm + rowF(u1));
+        const float2 phi = cmul(pr, bload2(rO, vO, sO + rowO(u1)));
+        const float2 ps = ld_psi(sm + rowF(u1));
+        const float2 d = make_float2(beta * (zp.x - phi.x), beta * (zp.y - phi.y));
+        const float2 pn = cadd(ps, d);
+        if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(u1));
+        else bstore2(rpsi, pn, vF, sm + rowF(u1));
+        e_d += cabs2(d);
+        e_n += cabs2(pn);
+        oacc[u1] = cadd(oacc[u1], cmulc(pr, pn));
+        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    const rsrc_t ropart = make_rsrc(sc.opart + (size_t)j * FF, (uint32_t)(FF * 8));
+#pragma unroll
+    for (int u1 = 0; u1 < 16; ++u1) {
+      if (NT_HINT) bstore2_nt(ropart, oacc[u1], vF, rowF(u1));
+      else bstore2(ropart, oacc[u1], vF, rowF(u1));
+    }
+    block_sum2<NT>(e_d, e_n, red);
+    if (t == 0) {
+      sc.err_psi[2 * j] = e_d;
+      sc.err_psi[2 * j + 1] = e_n;
+    }
+    __syncthreads();  // red and buf are reused by the next view
   }
 }
 

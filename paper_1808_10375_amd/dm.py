@@ -30,6 +30,10 @@ DM_BF16X3_DFT = 1
 DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 256)
 DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
 DM_FLAG_GRAPH = 4         # capture one iteration into a hipGraph and replay it
+DM_VIEWS_FUSED = 0            # dm_tuning.view_path values
+DM_VIEWS_THREE_KERNEL = 1
+DM_VIEWS_STREAMED = 2
+DM_VIEWS_STREAMED_CACHED = 3
 DM_MAX_MODES = 16
 DM_MAX_PROBE_CHUNKS = 64
 PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]
@@ -64,11 +68,11 @@ class dm_errors(ctypes.Structure):
 
 class dm_tuning(ctypes.Structure):
     _fields_ = [("obj_tile", ctypes.c_int32), ("probe_chunks", ctypes.c_int32),
-                ("multipass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("view_path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def to_dict(self) -> dict:
         return {"obj_tile": self.obj_tile, "probe_chunks": self.probe_chunks,
-                "multipass": self.multipass}
+                "view_path": self.view_path}
 
 
 class DMError(RuntimeError):
@@ -301,8 +305,8 @@ def dm_get_tuning(ctx) -> dm_tuning:
     return t
 
 
-def dm_set_tuning(ctx, obj_tile: int, probe_chunks: int, multipass: int = 0):
-    t = dm_tuning(int(obj_tile), int(probe_chunks), int(multipass), 0)
+def dm_set_tuning(ctx, obj_tile: int, probe_chunks: int, view_path: int = 0):
+    t = dm_tuning(int(obj_tile), int(probe_chunks), int(view_path), 0)
     _check(lib().dm_set_tuning(ctx, ctypes.byref(t)), ctx)
 
 
@@ -407,8 +411,8 @@ class DMContext:
     def tuning(self) -> dict:
         return dm_get_tuning(self.ctx).to_dict()
 
-    def set_tuning(self, obj_tile, probe_chunks, multipass=0):
-        dm_set_tuning(self.ctx, obj_tile, probe_chunks, multipass)
+    def set_tuning(self, obj_tile, probe_chunks, view_path=0):
+        dm_set_tuning(self.ctx, obj_tile, probe_chunks, view_path)
 
     def autotune(self, reps=5, cache_path=None) -> dict:
         return dm_autotune(self.ctx, reps, cache_path).to_dict()
@@ -488,8 +492,8 @@ class DMBatch:
     def tuning(self) -> dict:
         return dm_get_tuning(self.ctx).to_dict()
 
-    def set_tuning(self, obj_tile, probe_chunks, multipass=0):
-        dm_set_tuning(self.ctx, obj_tile, probe_chunks, multipass)
+    def set_tuning(self, obj_tile, probe_chunks, view_path=0):
+        dm_set_tuning(self.ctx, obj_tile, probe_chunks, view_path)
 
     def autotune(self, reps=5, cache_path=None) -> dict:
         return dm_autotune(self.ctx, reps, cache_path).to_dict()

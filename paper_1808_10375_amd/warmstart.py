@@ -56,14 +56,18 @@ def illumination(P0: np.ndarray, pos: np.ndarray, shape) -> np.ndarray:
     return acc
 
 
-def normalise_object(O: np.ndarray, weight: np.ndarray) -> np.ndarray:
+def normalise_object(O: np.ndarray, weight: np.ndarray, floor: float = 0.01) -> np.ndarray:
     """Remove the global factor c of the (P, O) -> (cP, O/c) ambiguity: over
     well-lit pixels the mean of O becomes real and positive and its RMS
-    amplitude 1 (the scale the flat initial object assumes)."""
+    amplitude 1 (the scale the flat initial object assumes).  Pixels whose
+    illumination is below `floor` of the peak are not determined by the data
+    (their Eq. 5 denominators are tiny) and are set to the flat value 1."""
     lit = weight >= 0.1 * weight.max()
     c = np.mean(O[lit])
     rms = math.sqrt(float(np.mean(np.abs(O[lit]) ** 2)))
-    return O * (np.conj(c) / abs(c)) / rms
+    out = O * (np.conj(c) / abs(c)) / rms
+    out[weight < floor * weight.max()] = 1.0
+    return out
 
 
 def patch_targets(O: np.ndarray, pos: np.ndarray, f: int = FRAME) -> np.ndarray:

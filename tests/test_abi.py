@@ -58,10 +58,17 @@ def test_workspace_bytes_valid_and_invalid():
     # F = 256 needs the multi-pass spectrum buffer as well
     d256 = desc(frame=256, obj_h=300, obj_w=300)
     assert dm.dm_workspace_bytes(d256) > 2 * 10 * 2 * 256 * 256 * 8
-    # so does the BF16x3 form, plus its 128 KB split DFT matrix
+    # the BF16x3 form holds a full spectrum buffer plus its 128 KB split DFT
+    # matrix; the FP32 path at F <= 128 holds spectra for at most 256 views
+    # in flight (one slot per persistent workgroup of the streamed kernel)
     f32 = desc(frame=128, obj_h=200, obj_w=200)
     b16 = desc(frame=128, obj_h=200, obj_w=200, precision=dm.DM_BF16X3_DFT)
-    assert dm.dm_workspace_bytes(b16) >= dm.dm_workspace_bytes(f32) + 10 * 2 * 128 * 128 * 8
+    assert dm.dm_workspace_bytes(b16) >= dm.dm_workspace_bytes(f32) + 128 * 1024
+    many = dict(frame=128, obj_h=200, obj_w=200, n_frames=600)
+    more = dict(many, n_frames=700)
+    per_view = 2 * 128 * 128 * 8 + 128 * 128 * (8 + 4) + 2 * 4 + 4 + 4
+    grown = dm.dm_workspace_bytes(desc(**more)) - dm.dm_workspace_bytes(desc(**many))
+    assert 100 * per_view <= grown <= 100 * per_view + 64 * 1024
 
 
 def _init_status(d, pos, ws_bytes=None, ptrs=(256, 256, 256, 256)):

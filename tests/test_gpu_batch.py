@@ -126,16 +126,17 @@ def test_graph_replays_equal_eager_launches():
     e.free()
 
 
-@pytest.mark.parametrize("tile,chunks,multipass", [(32, 16, 0), (16, 3, 0), (32, 64, 1)])
-def test_tunings_keep_parity(tile, chunks, multipass):
+@pytest.mark.parametrize("tile,chunks,view_path", [(32, 16, 0), (16, 3, 0), (32, 64, 1),
+                                                   (16, 16, 2), (32, 8, 3)])
+def test_tunings_keep_parity(tile, chunks, view_path):
     _torch()
     from paper_1808_10375_amd import dm
     c = synth.random_case(70, 27, 64, 3, 180, 170, perturb=0.5)
-    say(f"case tuning tile={tile} chunks={chunks} multipass={multipass}")
+    say(f"case tuning tile={tile} chunks={chunks} view_path={view_path}")
     sc = dict(I=c["I"], pos=c["pos"], P0=c["P"], O0=c["O"], beta=c["beta"])
-    ctx = single(sc, flags=dm.DM_FLAG_MULTIPASS if multipass else 0)
-    ctx.set_tuning(tile, chunks, multipass)
-    assert ctx.tuning() == {"obj_tile": tile, "probe_chunks": chunks, "multipass": multipass}
+    ctx = single(sc, flags=dm.DM_FLAG_MULTIPASS if view_path == 1 else 0)
+    ctx.set_tuning(tile, chunks, view_path)
+    assert ctx.tuning() == {"obj_tile": tile, "probe_chunks": chunks, "view_path": view_path}
     ctx.iterate(1)
     psi0 = oracle.init_views(c["P"], c["O"], c["pos"])
     _, P_o, O_o, _ = oracle.iterate(psi0, c["P"], c["O"], c["pos"], c["I"].astype(np.float64),
@@ -157,7 +158,7 @@ def test_autotune_picks_a_valid_tuning_and_restores_the_start(tmp_path):
     assert b.iterations == 0
     b.iterate(2)
     ref = dm.DMBatch(scans)
-    ref.set_tuning(t["obj_tile"], t["probe_chunks"], t["multipass"])
+    ref.set_tuning(t["obj_tile"], t["probe_chunks"], t["view_path"])
     ref.iterate(2)
     for s in range(2):
         assert rel(b.probe(s).cpu().numpy(), ref.probe(s).cpu().numpy()) == 0.0

@@ -38,7 +38,7 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_one_step(psi, P, O, I, pos, beta, flags=0, n_iter=1):
+def gpu_one_step(psi, P, O, I, pos, beta, flags=0, n_iter=1, view_path=None):
     torch = _torch()
     from paper_1808_10375_amd import dm
     dev = torch.device("cuda:0")
@@ -46,6 +46,9 @@ def gpu_one_step(psi, P, O, I, pos, beta, flags=0, n_iter=1):
     Pt = torch.from_numpy(np.ascontiguousarray(P, dtype=np.complex64)).to(dev)
     Ot = torch.from_numpy(np.ascontiguousarray(O, dtype=np.complex64)).to(dev)
     ctx = dm.DMContext(It, pos, Pt, Ot, beta=beta, flags=flags)
+    if view_path is not None:
+        t = ctx.tuning()
+        ctx.set_tuning(t["obj_tile"], t["probe_chunks"], view_path)
     psit = torch.from_numpy(np.ascontiguousarray(psi, dtype=np.complex64)).to(dev)
     ctx.set_state(psit, Pt, Ot, 0)
     ctx.iterate(n_iter)
@@ -74,7 +77,7 @@ def rel_weighted(a, b, w):
     return float(np.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2)))
 
 
-def one_step_case(case, flags=0, tol=TOL):
+def one_step_case(case, flags=0, tol=TOL, view_path=None):
     """psi' and P' to `tol` in plain relative L2.  O' to `tol` in relative L2
     weighted by the Eq. 5 denominator sum_j sum_k |P_k|^2 (the weight the
     views put on each object pixel: O' is their weighted least-squares fit),
@@ -88,7 +91,8 @@ def one_step_case(case, flags=0, tol=TOL):
                                           beta)
     den_o = oracle.object_update(psi_o, P.astype(np.complex128), O.astype(np.complex128),
                                  pos)[1]
-    psi_g, P_g, O_g, e_g, it = gpu_one_step(psi, P, O, I, pos, beta, flags)
+    psi_g, P_g, O_g, e_g, it = gpu_one_step(psi, P, O, I, pos, beta, flags,
+                                            view_path=view_path)
     r = (rel(psi_g, psi_o), rel_weighted(O_g, O_o, den_o), rel(P_g, P_o), rel(O_g, O_o))
     say(f"  rel L2 psi {r[0]:.2e}  O(weighted) {r[1]:.2e}  P {r[2]:.2e}  O(plain) {r[3]:.2e}"
         f"  eps_P gpu {e_g['eps_probe']:.6e} oracle {e_o['eps_probe']:.6e}")
@@ -113,6 +117,17 @@ SMALL = [
 def test_one_step_random_state(seed, n, f, m, h, w):
     say(f"case random seed={seed} N={n} F={f} M={m} obj={h}x{w}")
     one_step_case(synth.random_case(seed, n, f, m, h, w))
+
+
+@pytest.mark.parametrize("view_path", [2, 3])
+@pytest.mark.parametrize("seed,n,f,m,h,w", [(1, 37, 16, 1, 70, 53), (4, 41, 64, 3, 200, 170),
+                                            (5, 19, 128, 5, 300, 270),
+                                            (7, 11, 64, 16, 130, 130)])
+def test_one_step_streamed_path(seed, n, f, m, h, w, view_path):
+    """The persistent streamed view kernel (with and without the
+    non-temporal hint on psi)."""
+    say(f"case streamed view_path={view_path} seed={seed} N={n} F={f} M={m} obj={h}x{w}")
+    one_step_case(synth.random_case(seed, n, f, m, h, w), view_path=view_path)
 
 
 @pytest.mark.parametrize("seed,n,f,m,h,w,perturb", [(11, 13, 64, 2, 150, 140, None),
@@ -239,12 +254,15 @@ def test_nan_intensity_rejected():
     assert ex.value.status == dm.DM_E_ARG
 
 
-def test_multimode_2500x5_128_full_size_one_step():
-    """The 2500-view, 5-mode, 128x128 scan at full size, from its initial views."""
+@pytest.mark.parametrize("view_path", [0, 2])
+def test_multimode_2500x5_128_full_size_one_step(view_path):
+    """The 2500-view, 5-mode, 128x128 scan at full size, from its initial
+    views, through the fused and the streamed view kernels."""
     s = synth.multimode_spiral_128(1)
-    say("case 2500 views x 5 modes x 128^2 full size one step (oracle ~30 s)")
+    say(f"case 2500 views x 5 modes x 128^2 full size one step, view_path={view_path}")
     psi0 = oracle.init_views(s.P0, s.O0, s.pos).astype(np.complex64)
-    one_step_case(dict(psi=psi0, P=s.P0, O=s.O0, I=s.I, pos=s.pos, beta=0.8))
+    one_step_case(dict(psi=psi0, P=s.P0, O=s.O0, I=s.I, pos=s.pos, beta=0.8),
+                  view_path=view_path)
 
 
 def test_flyscan_256_strip_one_step():

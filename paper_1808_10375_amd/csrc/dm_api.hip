@@ -620,9 +620,9 @@ dm_status launch_views_mfma(dm_ctx* c) {
 }
 
 template <int F>
-dm_status launch_views_streamed(dm_ctx* c, bool nt) {
+dm_status launch_views_streamed(dm_ctx* c, int vp) {
   const int grid = std::min(c->total_views, c->stream_slots);
-  if (nt)
+  if (vp == DM_VIEWS_STREAMED)
     hipLaunchKernelGGL((dmk::k_fourier_stream<F, true>), dim3(grid), dim3(F * F / 16), 0,
                        c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
@@ -637,13 +637,12 @@ dm_status launch_views_streamed(dm_ctx* c, bool nt) {
 dm_status launch_views(dm_ctx* c) {
   if (c->bf16x3()) return launch_views_mfma(c);
   const int vp = c->tune.view_path;
-  if (vp == DM_VIEWS_STREAMED || vp == DM_VIEWS_STREAMED_CACHED) {
-    const bool nt = vp == DM_VIEWS_STREAMED;
+  if (vp >= DM_VIEWS_STREAMED) {
     switch (c->F) {
-      case 16: return launch_views_streamed<16>(c, nt);
-      case 32: return launch_views_streamed<32>(c, nt);
-      case 64: return launch_views_streamed<64>(c, nt);
-      case 128: return launch_views_streamed<128>(c, nt);
+      case 16: return launch_views_streamed<16>(c, vp);
+      case 32: return launch_views_streamed<32>(c, vp);
+      case 64: return launch_views_streamed<64>(c, vp);
+      case 128: return launch_views_streamed<128>(c, vp);
     }
   }
   if (vp == DM_VIEWS_FUSED) {

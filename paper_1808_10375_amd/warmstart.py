@@ -191,6 +191,13 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
     from .dm import DMBatch, DM_FLAG_GRAPH
     res = {}
     weights = [illumination(s.P0, s.pos, s.O0.shape) for s in scans]
+    # the network runs on the stream it was created on (the default one):
+    # all patches are made there before the batch's own stream starts
+    torch.cuda.synchronize(device)
+    t0 = time.time()
+    patches = [predict_patches(net, torch.as_tensor(s.I).to(device), batch) for s in scans]
+    torch.cuda.synchronize(device)
+    t_net = time.time() - t0
     stream = torch.cuda.Stream(device=device)
     for form in ("cold", "warm"):
         with torch.cuda.stream(stream):
@@ -198,15 +205,10 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
                         flags=DM_FLAG_GRAPH, stream=stream, device=device)
             t0 = time.time()
             if form == "warm":
-                # the network runs on its own stream: synchronise around it
-                for k, s in enumerate(scans):
-                    torch.cuda.synchronize(device)
-                    I = torch.as_tensor(s.I).to(device)
-                    p = predict_patches(net, I, batch)
-                    torch.cuda.synchronize(device)
-                    b.warm_start(k, p)
-                torch.cuda.synchronize(device)
-            t_init = time.time() - t0
+                for k in range(len(scans)):
+                    b.warm_start(k, patches[k])
+                stream.synchronize()
+            t_init = time.time() - t0 + (t_net if form == "warm" else 0.0)
             obj_err = {0: [object_error(b.object(k).cpu().numpy(), s.O_true, weights[k])
                            for k, s in enumerate(scans)]}
             done = 0
@@ -219,30 +221,34 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
             errs = [[e["eps_probe"] for e in b.error_history(k)] for k in range(len(scans))]
             b.free()
         res[form] = {"err": errs, "obj_err": obj_err, "init_s": t_init}
+    levels = (1e-3, 1e-2, 3e-2, 1e-1)
     out = {"n_iter": n_iter, "scans": len(scans), "per_scan": []}
     for k in range(len(scans)):
         ec, ew = res["cold"]["err"][k], res["warm"]["err"][k]
-        level = 1.1 * ec[-1]
         row = {
             "frames": int(scans[k].I.shape[0]),
-            "cold_final_err": ec[-1], "warm_final_err": ew[-1],
-            "iters_to_1e-3": {"cold": first_at_or_below(ec, 1e-3),
-                              "warm": first_at_or_below(ew, 1e-3)},
-            "iters_to_1.1x_cold_final": {"cold": first_at_or_below(ec, level),
-                                         "warm": first_at_or_below(ew, level)},
+            "err_at": {f: {str(i): e[i - 1] for i in (1, 2, 3, 5, 10, 20, 50, n_iter)
+                           if i <= len(e)}
+                       for f, e in (("cold", ec), ("warm", ew))},
+            "iters_to": {f"{lv:g}": {"cold": first_at_or_below(ec, lv),
+                                     "warm": first_at_or_below(ew, lv)} for lv in levels},
             "object_error": {f: {str(c): res[f]["obj_err"][c][k] for c in res[f]["obj_err"]}
                              for f in ("cold", "warm")},
         }
         out["per_scan"].append(row)
     out["warm_init_s"] = res["warm"]["init_s"]
 
-    def med(f, key):
-        v = [r[key][f] for r in out["per_scan"]]
-        v = [x for x in v if x is not None]
-        return float(np.median(v)) if v else None
+    def med_iters(lv, f):
+        v = [r["iters_to"][f"{lv:g}"][f] for r in out["per_scan"]]
+        reached = [x for x in v if x is not None]
+        return {"median": float(np.median(reached)) if reached else None,
+                "reached": len(reached)}
     out["median"] = {
-        key: {f: med(f, key) for f in ("cold", "warm")}
-        for key in ("iters_to_1e-3", "iters_to_1.1x_cold_final")}
+        "iters_to": {f"{lv:g}": {f: med_iters(lv, f) for f in ("cold", "warm")}
+                     for lv in levels},
+        "err_at": {f: {i: float(np.median([r["err_at"][f][i] for r in out["per_scan"]]))
+                       for i in out["per_scan"][0]["err_at"][f]}
+                   for f in ("cold", "warm")}}
     out["median_object_error"] = {
         f: {str(c): float(np.median(res[f]["obj_err"][c])) for c in res[f]["obj_err"]}
         for f in ("cold", "warm")}

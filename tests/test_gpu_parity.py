@@ -120,12 +120,13 @@ def test_one_step_random_state(seed, n, f, m, h, w):
 
 
 @pytest.mark.parametrize("view_path", [2, 3])
-@pytest.mark.parametrize("seed,n,f,m,h,w", [(1, 37, 16, 1, 70, 53), (4, 41, 64, 3, 200, 170),
+@pytest.mark.parametrize("seed,n,f,m,h,w", [(1, 37, 16, 1, 70, 53), (2, 37, 32, 2, 100, 90),
+                                            (4, 41, 64, 3, 200, 170),
                                             (5, 19, 128, 5, 300, 270),
                                             (7, 11, 64, 16, 130, 130)])
 def test_one_step_streamed_path(seed, n, f, m, h, w, view_path):
-    """The persistent streamed view kernel (with and without the
-    non-temporal hint on psi)."""
+    """The persistent streamed view kernel, with and without the
+    non-temporal hint on psi."""
     say(f"case streamed view_path={view_path} seed={seed} N={n} F={f} M={m} obj={h}x{w}")
     one_step_case(synth.random_case(seed, n, f, m, h, w), view_path=view_path)
 

@@ -26,6 +26,8 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr size_t kAlign = 256;
+// thread groups per object tile in the Eq. 5 gather (views in flight)
+constexpr int kObjGroups = 4;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -49,8 +51,11 @@ dm_tuning default_tuning(const dm_desc& d) {
   dm_tuning t{};
   t.obj_tile = 16;
   t.probe_chunks = default_chunks(d.frame);
+  // F = 128: the streamed kernel (the fused one cannot hold a view in
+  // registers there); smaller frames: the fused kernel
   t.view_path = (has_spectrum_buffer(d) && !is_bf16x3(d)) ? DM_VIEWS_THREE_KERNEL
-                                                              : DM_VIEWS_FUSED;
+                : (d.frame == 128 && !is_bf16x3(d))      ? DM_VIEWS_STREAMED
+                                                          : DM_VIEWS_FUSED;
   return t;
 }
 
@@ -674,10 +679,10 @@ dm_status launch_iteration(dm_ctx* c) {
   DM_TRY(phase_end(c, mk));
   DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
   if (c->tune.obj_tile == 16)
-    hipLaunchKernelGGL(dmk::k_object<16>, dim3(c->total_tiles), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
                        c->scan_dev(), c->tmap(), F);
   else
-    hipLaunchKernelGGL(dmk::k_object<32>, dim3(c->total_tiles), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
                        c->scan_dev(), c->tmap(), F);
   DM_LAUNCHED(c, "k_object");
   DM_TRY(phase_end(c, mk));
@@ -1095,10 +1100,10 @@ dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
   int first = 0;
   for (int t = 0; t < scan; ++t) first += c->scans[t].ntiles;
   if (c->tune.obj_tile == 16)
-    hipLaunchKernelGGL(dmk::k_object<16>, dim3(S.ntiles), dim3(256), 0, c->stream, c->scan_dev(),
+    hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(S.ntiles), dim3(256 * kObjGroups), 0, c->stream, c->scan_dev(),
                        c->tmap() + first, S.d.frame);
   else
-    hipLaunchKernelGGL(dmk::k_object<32>, dim3(S.ntiles), dim3(256), 0, c->stream, c->scan_dev(),
+    hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(S.ntiles), dim3(256 * kObjGroups), 0, c->stream, c->scan_dev(),
                        c->tmap() + first, S.d.frame);
   DM_LAUNCHED(c, "k_object (warm start)");
   hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes), dim3(256), 0, c->stream,

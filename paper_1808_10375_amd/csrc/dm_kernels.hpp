@@ -845,20 +845,25 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 }
 
 // ---------------------------------------------------------------------------
-// Object update (Eq. 5) as an atomics-free gather: one block of 256 threads
-// per T x T object tile walks the list of views whose window meets the tile,
-// in ascending view order, and sums their per-view numerators
-// sum_k conj(P_k) psi'_k and the mode power D = sum_k |P_k|^2.  Views are
-// taken four at a time so their loads are in flight together; each pixel
-// still adds them in ascending order.
+// Object update (Eq. 5) as an atomics-free gather: one block per T x T object
+// tile walks the list of views whose window meets the tile and sums their
+// per-view numerators sum_k conj(P_k) psi'_k and the mode power
+// D = sum_k |P_k|^2 (the normaliser, in double).  The block has G groups of
+// 256 threads; group q takes the views e = q, q + G, ... of the tile's list
+// (ascending), two at a time, so G * 2 views are in flight; the G partial
+// sums of each pixel are then added in group order through LDS.  The order of
+// every sum is fixed, so results are bitwise reproducible.
 // ---------------------------------------------------------------------------
-template <int T>
-__global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scans,
-                                                const int2* __restrict__ tmap, int F) {
+template <int T, int G>
+__global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ scans,
+                                                    const int2* __restrict__ tmap, int F) {
   constexpr int PPT = T * T / 256;  // pixels per thread
   constexpr int RSTEP = 256 / T;    // rows between a thread's pixels
-  __shared__ float red[8];
-  const int t = threadIdx.x;
+  __shared__ float red[2 * ((256 * G + 63) / 64)];
+  __shared__ float2 pnum[G > 1 ? (G - 1) : 1][T * T];
+  __shared__ double pden[G > 1 ? (G - 1) : 1][T * T];
+  const int q = threadIdx.x >> 8;   // group
+  const int t = threadIdx.x & 255;  // pixel lane within the group
   const int2 tm = tmap[blockIdx.x];
   const ScanDev& sc = scans[tm.x];
   const int tile = tm.y;
@@ -874,69 +879,89 @@ __global__ __launch_bounds__(256) void k_object(const ScanDev* __restrict__ scan
   const int col = t % T, row0 = t / T;
   const int cx = tx * T + col;
   const int ry = ty * T + row0;
-  // the normaliser sum_j sum_k |P_k|^2 accumulates in double
   float2 num[PPT];
   double den[PPT];
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) { num[q] = make_float2(0.f, 0.f); den[q] = 0.0; }
+  for (int k = 0; k < PPT; ++k) { num[k] = make_float2(0.f, 0.f); den[k] = 0.0; }
   const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   const size_t FF = (size_t)F * F;
-  constexpr int U = 4;
-  int e = e0;
-  for (; e + U <= e1; e += U) {
+  constexpr int U = 2;
+  int e = e0 + q;
+  for (; e + (U - 1) * G < e1; e += U * G) {
     float2 vv[U][PPT];
-    float dd[U][PPT];  // added to den in double below
+    float dd[U][PPT];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int jv = tile_views[e + k];
+    for (int u = 0; u < U; ++u) {
+      const int jv = tile_views[e + u * G];
       const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
       const int v = cx - xj;
       const float2* __restrict__ oj = opart + (size_t)jv * FF;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int u = ry + RSTEP * q - yj;
-        const bool in = ((unsigned)v < (unsigned)F) && ((unsigned)u < (unsigned)F);
-        vv[k][q] = in ? oj[(size_t)u * F + v] : make_float2(0.f, 0.f);
-        dd[k][q] = in ? D[u * F + v] : 0.f;
+      for (int k = 0; k < PPT; ++k) {
+        const int uu = ry + RSTEP * k - yj;
+        const bool in = ((unsigned)v < (unsigned)F) && ((unsigned)uu < (unsigned)F);
+        vv[u][k] = in ? oj[(size_t)uu * F + v] : make_float2(0.f, 0.f);
+        dd[u][k] = in ? D[uu * F + v] : 0.f;
       }
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        num[q] = cadd(num[q], vv[k][q]);
-        den[q] += (double)dd[k][q];
+      for (int k = 0; k < PPT; ++k) {
+        num[k] = cadd(num[k], vv[u][k]);
+        den[k] += (double)dd[u][k];
       }
   }
-  for (; e < e1; ++e) {
+  for (; e < e1; e += G) {
     const int jv = tile_views[e];
     const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
     const int v = cx - xj;
     const float2* __restrict__ oj = opart + (size_t)jv * FF;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int u = ry + RSTEP * q - yj;
-      if (((unsigned)v < (unsigned)F) && ((unsigned)u < (unsigned)F)) {
-        num[q] = cadd(num[q], oj[(size_t)u * F + v]);
-        den[q] += (double)D[u * F + v];
+    for (int k = 0; k < PPT; ++k) {
+      const int uu = ry + RSTEP * k - yj;
+      if (((unsigned)v < (unsigned)F) && ((unsigned)uu < (unsigned)F)) {
+        num[k] = cadd(num[k], oj[(size_t)uu * F + v]);
+        den[k] += (double)D[uu * F + v];
       }
     }
   }
-  float e_d = 0.f, e_n = 0.f;
+  if constexpr (G > 1) {
+    if (q > 0) {
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int r = ry + RSTEP * q;
-    if (r < H && cx < W && den[q] > 0.0) {
-      const float inv = (float)(1.0 / den[q]);
-      const float2 on = make_float2(num[q].x * inv, num[q].y * inv);
-      const float2 oo = O[(size_t)r * W + cx];
-      e_d += cabs2(csub(on, oo));
-      e_n += cabs2(on);
-      O[(size_t)r * W + cx] = on;
+      for (int k = 0; k < PPT; ++k) {
+        pnum[q - 1][t + 256 * k] = num[k];
+        pden[q - 1][t + 256 * k] = den[k];
+      }
+    }
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+      for (int g = 0; g < G - 1; ++g)
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          num[k] = cadd(num[k], pnum[g][t + 256 * k]);
+          den[k] += pden[g][t + 256 * k];
+        }
     }
   }
-  block_sum2<256>(e_d, e_n, red);
-  if (t == 0) {
+  float e_d = 0.f, e_n = 0.f;
+  if (q == 0) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int r = ry + RSTEP * k;
+      if (r < H && cx < W && den[k] > 0.0) {
+        const float inv = (float)(1.0 / den[k]);
+        const float2 on = make_float2(num[k].x * inv, num[k].y * inv);
+        const float2 oo = O[(size_t)r * W + cx];
+        e_d += cabs2(csub(on, oo));
+        e_n += cabs2(on);
+        O[(size_t)r * W + cx] = on;
+      }
+    }
+  }
+  block_sum2<256 * G>(e_d, e_n, red);
+  if (threadIdx.x == 0) {
     err_obj[2 * tile] = e_d;
     err_obj[2 * tile + 1] = e_n;
   }

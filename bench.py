@@ -39,17 +39,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch_key: str):
+def measured_traffic(launch_key: str, kernel: str):
     """HBM bytes per launch of the view kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
+    counter summary, if it was taken on the current kernel sources, the same
+    workload and the same view kernel."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != launch_key:
+    if (t.get("kernel_hash") != kernel_hash() or t.get("workload") != launch_key
+            or kernel not in t.get("kernel", "")):
         return None
     return t.get("bytes_per_launch")
+
+
+# rocprofv3 name of the view kernel of each view path at frame size f
+def view_kernel_name(view_path: int, f: int) -> str:
+    return {0: f"k_fourier_fused<{f}, 1>", 1: f"k_rows_fwd<{f}>",
+            2: f"k_fourier_stream<{f}, true, false>",
+            3: f"k_fourier_stream<{f}, false, false>",
+            4: f"k_fourier_stream<{f}, true, true>"}[view_path]
 
 
 def views_alg_bytes(n, m, f):
@@ -218,7 +228,7 @@ def main():
                     help="skip the batched-scans (and other forms') measurements")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="transform form of the headline run (bf16x3: F = 128 only)")
-    ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3],
+    ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3, 4],
                     help="override the library's default view kernel (dm_tuning.view_path)")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")
@@ -291,7 +301,7 @@ def main():
     alg = views_alg_bytes(n, m, f)
     achieved = alg / (views_ms * 1e-3) / 1e9
     key = f"n{n}_m{m}_f{f}_o{h}x{w}"
-    traffic = measured_traffic(key)
+    traffic = measured_traffic(key, view_kernel_name(view_path, f))
     errs = [e["eps_probe"] for e in hist]
     reach = next((i + 1 for i, e in enumerate(errs) if e <= 1e-3), None)
 
@@ -315,9 +325,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": {0: "k_fourier_fused<%d>" % f, 1: "views (3 kernels)",
-                                2: "k_fourier_stream<%d>" % f,
-                                3: "k_fourier_stream<%d> (cached psi)" % f}[view_path],
+                     "kernel": (view_kernel_name(view_path, f) if view_path != 1
+                                else "views (3 kernels)"),
                      "alg_bytes_per_launch": alg, "avg_launch_ms": views_ms},
         "step_roofline_frac": step_alg_bytes(n, m, f) / (ms_per_step * 1e-3) / 1e9
         / HBM_PEAK_GBS,

@@ -132,6 +132,10 @@ typedef struct {
                                       and stored with the non-temporal hint
                                       (F <= 128)                             */
 #define DM_VIEWS_STREAMED_CACHED 3 /* the same with ordinary psi accesses    */
+#define DM_VIEWS_STREAMED_MERGED 4 /* DM_VIEWS_STREAMED with the view update
+                                      right after each inverse transform (the
+                                      updated spectra make one trip through
+                                      the slot instead of two)               */
 
 /* Launch shapes chosen per context (dm_set_tuning / dm_autotune).  They
  * change the speed of an iteration and the summation order of the probe
@@ -146,8 +150,8 @@ typedef struct {
                             DM_VIEWS_FUSED, DM_VIEWS_THREE_KERNEL (only
                             where the workspace holds its spectrum buffer:
                             F = 256 or DM_FLAG_MULTIPASS at init; forced for
-                            F = 256), DM_VIEWS_STREAMED or
-                            DM_VIEWS_STREAMED_CACHED (F <= 128); ignored by
+                            F = 256), or one of the DM_VIEWS_STREAMED*
+                            paths (F <= 128); ignored by
                             the BF16x3 form, which must be given 0        */
   int32_t reserved;      /* must be 0                                     */
 } dm_tuning;

@@ -51,10 +51,10 @@ dm_tuning default_tuning(const dm_desc& d) {
   dm_tuning t{};
   t.obj_tile = 16;
   t.probe_chunks = default_chunks(d.frame);
-  // F = 128: the streamed kernel (the fused one cannot hold a view in
-  // registers there); smaller frames: the fused kernel
+  // F = 128: the streamed kernel with the merged update (the fused one
+  // cannot hold a view in registers there); smaller frames: the fused kernel
   t.view_path = (has_spectrum_buffer(d) && !is_bf16x3(d)) ? DM_VIEWS_THREE_KERNEL
-                : (d.frame == 128 && !is_bf16x3(d))      ? DM_VIEWS_STREAMED
+                : (d.frame == 128 && !is_bf16x3(d))      ? DM_VIEWS_STREAMED_MERGED
                                                           : DM_VIEWS_FUSED;
   return t;
 }
@@ -163,11 +163,11 @@ CtxLayout ctx_layout(int n_scans, const dm_desc* d) {
   C.cmap = take(sizeof(int2) * (size_t)DM_MAX_PROBE_CHUNKS * n_scans);
   C.tw = take(sizeof(float2) * d[0].frame);
   C.wf = is_bf16x3(d[0]) ? take(sizeof(uint4) * dmk::kMfWords) : 0;
-  // spectra of the view in hand, per persistent workgroup of the streamed
-  // path: [slot][M][F][F] complex64
+  // spectra of the view in hand and its modulus scale, per persistent
+  // workgroup of the streamed path: [slot]([M][F][F] complex64, [F][F] float)
   C.vscr = (!is_bf16x3(d[0]) && d[0].frame <= 128)
-               ? take((size_t)stream_slots(n_scans, d) * d[0].n_modes * d[0].frame *
-                      d[0].frame * 8)
+               ? take((size_t)stream_slots(n_scans, d) * d[0].frame * d[0].frame *
+                      (8 * (size_t)d[0].n_modes + 4))
                : 0;
   C.flags = take(sizeof(int));
   C.header = off;
@@ -628,11 +628,15 @@ template <int F>
 dm_status launch_views_streamed(dm_ctx* c, int vp) {
   const int grid = std::min(c->total_views, c->stream_slots);
   if (vp == DM_VIEWS_STREAMED)
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true>), dim3(grid), dim3(F * F / 16), 0,
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true, false>), dim3(grid), dim3(F * F / 16), 0,
+                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+                       c->vscr());
+  else if (vp == DM_VIEWS_STREAMED_CACHED)
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, false, false>), dim3(grid), dim3(F * F / 16), 0,
                        c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
   else
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, false>), dim3(grid), dim3(F * F / 16), 0,
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true, true>), dim3(grid), dim3(F * F / 16), 0,
                        c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
   DM_LAUNCHED(c, "k_fourier_stream");
@@ -962,7 +966,7 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     c->err = "probe_chunks out of range";
     return DM_E_ARG;
   }
-  if (t.reserved != 0 || t.view_path < DM_VIEWS_FUSED || t.view_path > DM_VIEWS_STREAMED_CACHED) {
+  if (t.reserved != 0 || t.view_path < DM_VIEWS_FUSED || t.view_path > DM_VIEWS_STREAMED_MERGED) {
     c->err = "bad tuning fields";
     return DM_E_ARG;
   }
@@ -1264,7 +1268,7 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   const int chunk_opts[3] = {std::max(1, base.probe_chunks / 2), base.probe_chunks,
                              std::min(DM_MAX_PROBE_CHUNKS, base.probe_chunks * 2)};
   const bool have_spec = c->scans[0].L.tspec != 0 && !c->bf16x3();
-  for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_CACHED; ++mp) {
+  for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_MERGED; ++mp) {
     if (c->bf16x3() && mp != DM_VIEWS_FUSED) continue;
     if (mp == DM_VIEWS_THREE_KERNEL && !have_spec) continue;
     if (mp != DM_VIEWS_THREE_KERNEL && c->F > 128) continue;

@@ -183,6 +183,14 @@ __device__ __forceinline__ void bstore2_nt(rsrc_t r, float2 x, int voff, int sof
   __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
 }
 
+// A value every lane of the wave holds alike (a view index, a position, an
+// object width read from memory), moved to an SGPR so that buffer offsets
+// built from it are scalar; without it the compiler cannot prove uniformity
+// of values loaded through pointers it cannot show read-only, and wraps
+// each buffer access that takes it as its scalar offset in a readfirstlane
+// loop.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // Index that is the same for every lane of a wave when F >= 64 (a wave's 64
 // lanes then share t / F); keeping it in an SGPR makes its table loads scalar.
 template <int F>

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
   __syncthreads();  // the twiddles are read by every wave
   const int2 vm = vmap[xcd_slot(blockIdx.x, total)];
   const ScanDev& sc = scans[vm.x];
-  const int j = vm.y;
+  const int j = uni(vm.y);
   float2* __restrict__ psi = sc.psi;
   const float* __restrict__ I = sc.I;
   const float2* __restrict__ P = sc.P;
@@ -333,11 +333,11 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
   float2* __restrict__ opart = sc.opart;
   float* __restrict__ gscr = sc.gscr;
   float* __restrict__ err_psi = sc.err_psi;
-  const int H = sc.H, W = sc.W;
+  const int H = uni(sc.H), W = uni(sc.W);
   const float beta = sc.beta;
   const int c = t % F;
   const int g0 = wave_uniform_div<F>(t);
-  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   // buffers: this view's modes, the probe, the object, this view's scale
   const rsrc_t rpsi = make_rsrc(psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
   const rsrc_t rP = make_rsrc(P, (uint32_t)(M * FF * 8));
@@ -446,21 +446,33 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
       for (int r = 0; r < 16; ++r)
         a[v][r] = cscale(a[v][r], bload1(rg, vG, (v * 16 + r) * NT * 4));
     Frame2D<F, 1, V>::inv(a, buf, twl, c, g0);
+    // the psi' stores may alias later loads as far as the compiler knows:
+    // each batch issues its loads before any of its stores
+    constexpr int KB = 4;
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) {
-        const float2 pr = bload2(rP, vF, sm + rowF(v, u1));
-        const float2 phi = cmul(pr, bload2(rO, vO, sO + rowO(v, u1)));
-        const float2 ps = kHold ? hold[kHold ? v : 0][kHold ? u1 : 0]
-                                : bload2(rpsi, vF, sm + rowF(v, u1));
-        const float2 d = make_float2(beta * (a[v][u1].x - phi.x), beta * (a[v][u1].y - phi.y));
-        const float2 pn = cadd(ps, d);
-        bstore2(rpsi, pn, vF, sm + rowF(v, u1));
-        e_d += cabs2(d);
-        e_n += cabs2(pn);
-        oacc[v][u1] = cadd(oacc[v][u1], cmulc(pr, pn));
-        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int b = 0; b < 16; b += KB) {
+        float2 pr[KB], ov[KB], pv[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          pr[k] = bload2(rP, vF, sm + rowF(v, b + k));
+          ov[k] = bload2(rO, vO, sO + rowO(v, b + k));
+          pv[k] = kHold ? hold[kHold ? v : 0][kHold ? b + k : 0]
+                        : bload2(rpsi, vF, sm + rowF(v, b + k));
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const int u1 = b + k;
+          const float2 phi = cmul(pr[k], ov[k]);
+          const float2 d =
+              make_float2(beta * (a[v][u1].x - phi.x), beta * (a[v][u1].y - phi.y));
+          const float2 pn = cadd(pv[k], d);
+          bstore2(rpsi, pn, vF, sm + rowF(v, u1));
+          e_d += cabs2(d);
+          e_n += cabs2(pn);
+          oacc[v][u1] = cadd(oacc[v][u1], cmulc(pr[k], pn));
+        }
       }
   }
 
@@ -493,7 +505,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
 // once with the non-temporal hint (NT) so the probe and the object stay in
 // L2; the slot's scratch is rewritten view after view and stays in cache.
 // ---------------------------------------------------------------------------
-template <int F, bool NT_HINT>
+template <int F, bool NT_HINT, bool MERGE>
 __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
     const float2* __restrict__ tw, int M, float2* __restrict__ vscr) {
@@ -510,17 +522,21 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
   __syncthreads();
   const int c = t % F;
   const int g0 = wave_uniform_div<F>(t);
-  const rsrc_t rs = make_rsrc(vscr + (size_t)blockIdx.x * M * FF, (uint32_t)(M * FF * 8));
+  // slot: the spectra [M][16][NT] complex, then the modulus scale [16][NT]
+  const size_t slot_words = (size_t)M * FF * 2 + FF;
+  float* const slot = reinterpret_cast<float*>(vscr) + (size_t)blockIdx.x * slot_words;
+  const rsrc_t rs = make_rsrc(slot, (uint32_t)(slot_words * 4));
+  const int sG = M * FF * 8;  // byte offset of the scale in the slot
   const int vS = t * 8;  // scratch: [mode][r][thread]
   auto rowS = [&](int m, int r) { return (m * 16 + r) * NT * 8; };
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int2 vm = vmap[xcd_slot(item, total)];
     const ScanDev& sc = scans[vm.x];
-    const int j = vm.y;
-    const int H = sc.H, W = sc.W;
+    const int j = uni(vm.y);
+    const int H = uni(sc.H), W = uni(sc.W);
     const float beta = sc.beta;
-    const int y0 = sc.pos[2 * j], x0 = sc.pos[2 * j + 1];
+    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
     const rsrc_t rpsi = make_rsrc(sc.psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
     const rsrc_t rP = make_rsrc(sc.P, (uint32_t)(M * FF * 8));
     const rsrc_t rO = make_rsrc(sc.O, (uint32_t)((size_t)H * W * 8));
@@ -535,15 +551,23 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
     float S[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) S[r] = 0.f;
-    // ---- pass 1
+    // ---- pass 1 (loads in batches, all of a batch issued before its use)
     for (int m = 0; m < M; ++m) {
       const int sm = m * FF * 8;
 #pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) {
-        const float2 ps = ld_psi(sm + rowF(u1));
-        const float2 phi = cmul(bload2(rP, vF, sm + rowF(u1)), bload2(rO, vO, sO + rowO(u1)));
-        a[0][u1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int b = 0; b < 16; b += 8) {
+        float2 ps[8], pp[8], oo[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          ps[k] = ld_psi(sm + rowF(b + k));
+          pp[k] = bload2(rP, vF, sm + rowF(b + k));
+          oo[k] = bload2(rO, vO, sO + rowO(b + k));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float2 phi = cmul(pp[k], oo[k]);
+          a[0][b + k] = make_float2(2.f * phi.x - ps[k].x, 2.f * phi.y - ps[k].y);
+        }
       }
       Frame2D<F, -1, 1>::fwd(a, buf, twl, c, g0);
 #pragma unroll
@@ -572,36 +596,72 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
         }
       __syncthreads();  // bI aliases the exchange buffer
     }
-    // ---- pass 2: scaled spectra back to the spatial domain
-    for (int m = 0; m < M; ++m) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) a[0][r] = cscale(bload2(rs, vS, rowS(m, r)), S[r]);
-      Frame2D<F, 1, 1>::inv(a, buf, twl, c, g0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) bstore2(rs, a[0][r], vS, rowS(m, r));
-    }
-    // ---- pass 3: view update and the object numerator
     float2 oacc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
     float e_d = 0.f, e_n = 0.f;
-    for (int m = 0; m < M; ++m) {
+    // The stores of psi' may alias later loads as far as the compiler knows,
+    // so no load is moved above a store: every batch issues all of its loads
+    // first, then computes and stores.
+    constexpr int KB = 4;  // elements per batch
+    // view update of mode m from Z' (zp(k) gives element b + k)
+    auto update = [&](int m, auto zp_of) {
       const int sm = m * FF * 8;
 #pragma unroll
-      for (int u1 = 0; u1 < 16; ++u1) {
-        const float2 zp = bload2(rs, vS, rowS(m, u1));
-        const float2 pr = bload2(rP, vF, sm + rowF(u1));
-        const float2 phi = cmul(pr, bload2(rO, vO, sO + rowO(u1)));
-        const float2 ps = ld_psi(sm + rowF(u1));
-        const float2 d = make_float2(beta * (zp.x - phi.x), beta * (zp.y - phi.y));
-        const float2 pn = cadd(ps, d);
-        if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(u1));
-        else bstore2(rpsi, pn, vF, sm + rowF(u1));
-        e_d += cabs2(d);
-        e_n += cabs2(pn);
-        oacc[u1] = cadd(oacc[u1], cmulc(pr, pn));
-        if ((u1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int b = 0; b < 16; b += KB) {
+        float2 zp[KB], pr[KB], ov[KB], ps[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          zp[k] = zp_of(b + k);
+          pr[k] = bload2(rP, vF, sm + rowF(b + k));
+          ov[k] = bload2(rO, vO, sO + rowO(b + k));
+          ps[k] = ld_psi(sm + rowF(b + k));
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const float2 phi = cmul(pr[k], ov[k]);
+          const float2 d = make_float2(beta * (zp[k].x - phi.x), beta * (zp[k].y - phi.y));
+          const float2 pn = cadd(ps[k], d);
+          if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(b + k));
+          else bstore2(rpsi, pn, vF, sm + rowF(b + k));
+          e_d += cabs2(d);
+          e_n += cabs2(pn);
+          oacc[b + k] = cadd(oacc[b + k], cmulc(pr[k], pn));
+        }
       }
+    };
+    // ---- pass 2: scaled spectra back to the spatial domain; with MERGE the
+    // view update follows each inverse transform directly (the object
+    // numerator stays live through the transforms, and the scale is parked
+    // in the slot to make room for it), otherwise Z' goes back to the slot
+    // and pass 3 updates
+    if constexpr (MERGE) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[r]), rs, t * 4,
+                                              sG + r * NT * 4, 0);
+    }
+    for (int m = 0; m < M; ++m) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a[0][r] = bload2(rs, vS, rowS(m, r));
+      if constexpr (MERGE) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a[0][r] = cscale(a[0][r], bload1(rs, t * 4, sG + r * NT * 4));
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a[0][r] = cscale(a[0][r], S[r]);
+      }
+      Frame2D<F, 1, 1>::inv(a, buf, twl, c, g0);
+      if constexpr (MERGE) {
+        update(m, [&](int u) { return a[0][u]; });
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) bstore2(rs, a[0][r], vS, rowS(m, r));
+      }
+    }
+    // ---- pass 3: view update and the object numerator
+    if constexpr (!MERGE) {
+      for (int m = 0; m < M; ++m) update(m, [&](int u) { return bload2(rs, vS, rowS(m, u)); });
     }
     const rsrc_t ropart = make_rsrc(sc.opart + (size_t)j * FF, (uint32_t)(FF * 8));
 #pragma unroll
@@ -640,17 +700,17 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
   const int t = threadIdx.x;
   const int2 vm = vmap[blockIdx.x / M];
   const ScanDev& sc = scans[vm.x];
-  const int j = vm.y, m = blockIdx.x % M;
+  const int j = uni(vm.y), m = blockIdx.x % M;
   const int jm = j * M + m;
   const float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
   const int* __restrict__ pos = sc.pos;
   float2* __restrict__ T = sc.tspec;
-  const int W = sc.W;
+  const int W = uni(sc.W);
   const int rl = t / B, n2 = t % B;
   const int row = blockIdx.y * RB + rl;
-  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   const float2* __restrict__ pm = psi + (size_t)jm * FF + (size_t)row * F;
   const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
   const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
@@ -695,7 +755,7 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
   const int t = threadIdx.x;
   const int2 vm = vmap[blockIdx.x];
   const ScanDev& sc = scans[vm.x];
-  const int j = vm.y;
+  const int j = uni(vm.y);
   float2* __restrict__ T = sc.tspec;
   const float* __restrict__ I = sc.I;
   const int col0 = blockIdx.y * CB;
@@ -777,7 +837,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(
   const int t = threadIdx.x;
   const int2 vm = vmap[blockIdx.x];
   const ScanDev& sc = scans[vm.x];
-  const int j = vm.y;
+  const int j = uni(vm.y);
   float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
@@ -785,11 +845,11 @@ __global__ __launch_bounds__(256) void k_rows_inv(
   const float2* __restrict__ T = sc.tspec;
   float2* __restrict__ opart = sc.opart;
   float* __restrict__ err_psi = sc.err_psi;
-  const int W = sc.W;
+  const int W = uni(sc.W);
   const float beta = sc.beta;
   const int rl = t / B, n2 = t % B;
   const int row = blockIdx.y * RB + rl;
-  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
   float2 oacc[16];
 #pragma unroll
@@ -874,7 +934,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   const int* __restrict__ tile_ptr = sc.tile_ptr;
   const int* __restrict__ tile_views = sc.tile_views;
   float* __restrict__ err_obj = sc.err_obj;
-  const int H = sc.H, W = sc.W, tiles_x = sc.tiles_x;
+  const int H = uni(sc.H), W = uni(sc.W), tiles_x = uni(sc.tiles_x);
   const int ty = tile / tiles_x, tx = tile % tiles_x;
   const int col = t % T, row0 = t / T;
   const int cx = tx * T + col;
@@ -1151,7 +1211,7 @@ __global__ __launch_bounds__(256) void k_init_psi(float2* __restrict__ psi,
   const int jm = blockIdx.x;
   const int j = jm / M, m = jm % M;
   const int FF = F * F;
-  const int y0 = pos[2 * j], x0 = pos[2 * j + 1];
+  const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   for (int p = threadIdx.x; p < FF; p += blockDim.x) {
     const int u = p / F, v = p % F;
     psi[(size_t)jm * FF + p] = cmul(P[(size_t)m * FF + p], O[(size_t)(y0 + u) * W + x0 + v]);

@@ -136,9 +136,9 @@ __global__ __launch_bounds__(256) void k_mf_rows_fwd(const ScanDev* __restrict__
     const int2 vm = vmap[item / M];
     const int m = item % M;
     const ScanDev& sc = scans[vm.x];
-    const int j = vm.y;
-    const int W = sc.W;
-    const int y0 = sc.pos[2 * j], x0 = sc.pos[2 * j + 1];
+    const int j = uni(vm.y);
+    const int W = uni(sc.W);
+    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
     const float2* __restrict__ psi = sc.psi + ((size_t)j * M + m) * FF;
     const float2* __restrict__ P = sc.P + (size_t)m * FF;
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
     const int2 vm = vmap[item / kMfNt];
     const int n0 = 16 * (item % kMfNt);
     const ScanDev& sc = scans[vm.x];
-    const int j = vm.y;
+    const int j = uni(vm.y);
     float2* __restrict__ T = sc.tspec + (size_t)j * M * FF;
     const float* __restrict__ I = sc.I + (size_t)j * FF;
     mf_f32x4 ure[kMfMaxModes][2], uim[kMfMaxModes][2];
@@ -337,10 +337,10 @@ __global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__
     const int2 vm = vmap[item >> 1];
     const int h = item & 1;
     const ScanDev& sc = scans[vm.x];
-    const int j = vm.y;
-    const int W = sc.W;
+    const int j = uni(vm.y);
+    const int W = uni(sc.W);
     const float beta = sc.beta;
-    const int y0 = sc.pos[2 * j], x0 = sc.pos[2 * j + 1];
+    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
     const int rbase = 64 * h + 16 * wave;
     float2 oacc[kMfNt][4];

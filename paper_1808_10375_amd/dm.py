@@ -34,6 +34,7 @@ DM_VIEWS_FUSED = 0            # dm_tuning.view_path values
 DM_VIEWS_THREE_KERNEL = 1
 DM_VIEWS_STREAMED = 2
 DM_VIEWS_STREAMED_CACHED = 3
+DM_VIEWS_STREAMED_MERGED = 4
 DM_MAX_MODES = 16
 DM_MAX_PROBE_CHUNKS = 64
 PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]

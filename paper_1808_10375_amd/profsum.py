@@ -22,7 +22,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-VIEW_KERNEL = "k_fourier_fused"
+VIEW_KERNEL = "k_fourier_"  # the fused or streamed view kernel
 
 
 def short(name: str) -> str:

@@ -63,7 +63,12 @@ def test_workspace_bytes_valid_and_invalid():
     # in flight (one slot per persistent workgroup of the streamed kernel)
     f32 = desc(frame=128, obj_h=200, obj_w=200)
     b16 = desc(frame=128, obj_h=200, obj_w=200, precision=dm.DM_BF16X3_DFT)
-    assert dm.dm_workspace_bytes(b16) >= dm.dm_workspace_bytes(f32) + 128 * 1024
+    ff = 128 * 128
+    # BF16x3: spectrum buffer [N][M][F][F] + split DFT matrix; FP32: one slot
+    # per view in flight (here all 10) of M spectra and a float scale
+    expect = (10 * 2 * ff * 8 + 128 * 1024) - 10 * ff * (8 * 2 + 4)
+    got = dm.dm_workspace_bytes(b16) - dm.dm_workspace_bytes(f32)
+    assert abs(got - expect) <= 4096, (got, expect)
     many = dict(frame=128, obj_h=200, obj_w=200, n_frames=600)
     more = dict(many, n_frames=700)
     per_view = 2 * 128 * 128 * 8 + 128 * 128 * (8 + 4) + 2 * 4 + 4 + 4

@@ -119,7 +119,7 @@ def test_one_step_random_state(seed, n, f, m, h, w):
     one_step_case(synth.random_case(seed, n, f, m, h, w))
 
 
-@pytest.mark.parametrize("view_path", [2, 3])
+@pytest.mark.parametrize("view_path", [2, 3, 4])
 @pytest.mark.parametrize("seed,n,f,m,h,w", [(1, 37, 16, 1, 70, 53), (2, 37, 32, 2, 100, 90),
                                             (4, 41, 64, 3, 200, 170),
                                             (5, 19, 128, 5, 300, 270),
@@ -255,7 +255,7 @@ def test_nan_intensity_rejected():
     assert ex.value.status == dm.DM_E_ARG
 
 
-@pytest.mark.parametrize("view_path", [0, 2])
+@pytest.mark.parametrize("view_path", [0, 2, 4])
 def test_multimode_2500x5_128_full_size_one_step(view_path):
     """The 2500-view, 5-mode, 128x128 scan at full size, from its initial
     views, through the fused and the streamed view kernels."""

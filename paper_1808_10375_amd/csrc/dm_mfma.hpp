@@ -371,21 +371,31 @@ __global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__
           mf_cmma<true>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
                         mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), re[nt], im[nt]);
       }
+      // the psi' stores may alias later loads as far as the compiler knows:
+      // each tile's loads are issued before its stores
 #pragma unroll
-      for (int nt = 0; nt < kMfNt; ++nt)
+      for (int nt = 0; nt < kMfNt; ++nt) {
+        const int col = 16 * nt + (lane & 15);
+        float2 pr[4], ov[4], pv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = rbase + 4 * (lane >> 4) + r;
-          const int col = 16 * nt + (lane & 15);
-          const float2 pr = P[row * F + col];
-          const float2 phi = cmul(pr, O[(size_t)row * W + col]);
+          pr[r] = P[row * F + col];
+          ov[r] = O[(size_t)row * W + col];
+          pv[r] = psi[row * F + col];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rbase + 4 * (lane >> 4) + r;
+          const float2 phi = cmul(pr[r], ov[r]);
           const float2 d = make_float2(beta * (re[nt][r] - phi.x), beta * (im[nt][r] - phi.y));
-          const float2 pn = cadd(psi[row * F + col], d);
+          const float2 pn = cadd(pv[r], d);
           psi[row * F + col] = pn;
           e_d += cabs2(d);
           e_n += cabs2(pn);
-          oacc[nt][r] = cadd(oacc[nt][r], cmulc(pr, pn));
+          oacc[nt][r] = cadd(oacc[nt][r], cmulc(pr[r], pn));
         }
+      }
     }
     float2* __restrict__ oj = sc.opart + (size_t)j * FF;
 #pragma unroll

@@ -20,8 +20,13 @@
  *   head    1x1 convolution C0 -> 2 (real, imaginary part of the patch)
  *   loss    mean squared error over all outputs; Adam optimiser
  * Weights are stored as bfloat16 (round to nearest even from float32 master
- * copies) and used with float32 accumulation; DMNET_FLAG_FP32_WEIGHTS uses
- * the float32 masters directly (for gradient checks).
+ * copies); biases stay float32 and bias gradients sum the unrounded output
+ * gradients.  Every 3x3 convolution (forward, data gradient, weight gradient)
+ * runs on the matrix cores as an implicit GEMM with bfloat16 operands -- its
+ * input activations and output gradients rounded to nearest even -- and
+ * float32 accumulation; the 1x1 head runs on the vector units with float32
+ * activations.  DMNET_FLAG_FP32_WEIGHTS uses the float32 masters and float32
+ * activations throughout, on the vector units (for gradient checks).
  *
  * Parameter vector (float32, dmnet_n_params entries): for each convolution in
  * the order enc0a, enc0b, enc1a, ..., enc(L-1)b, dec(L-2)a, dec(L-2)b, ...,

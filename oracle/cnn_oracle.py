@@ -139,32 +139,41 @@ def upsample2_backward(dy):
 # ---------------------------------------------------------------------------
 # the network
 # ---------------------------------------------------------------------------
-def forward(params, x, levels: int = 4):
-    """Returns (y, cache).  x: [N][1][S][S]."""
+def _ident(v):
+    return v
+
+
+def forward(params, x, levels: int = 4, act_round=None):
+    """Returns (y, cache).  x: [N][1][S][S].
+
+    act_round, if given, is applied to the input of every 3x3 convolution
+    (the form in which the matrix cores take bfloat16 activations); the
+    cache keeps the rounded inputs, which the backward pass then uses."""
+    r = act_round or _ident
     it = iter(range(0, len(params), 2))
     cache = {"enc_in": [], "enc_mid": [], "enc_out": [], "dec_in": [], "dec_mid": [],
-             "dec_out": []}
+             "dec_out": [], "act_round": act_round}
     h = x
     skips = []
     for l in range(levels):
         i = next(it)
-        cache["enc_in"].append(h)
-        a = np.maximum(conv3x3(h, params[i], params[i + 1]), 0.0)
+        cache["enc_in"].append(r(h))
+        a = np.maximum(conv3x3(r(h), params[i], params[i + 1]), 0.0)
         cache["enc_mid"].append(a)
         i = next(it)
-        h = np.maximum(conv3x3(a, params[i], params[i + 1]), 0.0)
+        h = np.maximum(conv3x3(r(a), params[i], params[i + 1]), 0.0)
         cache["enc_out"].append(h)
         skips.append(h)
         if l < levels - 1:
             h = avgpool2(h)
     for l in range(levels - 2, -1, -1):
         u = np.concatenate([upsample2(h), skips[l]], axis=1)
-        cache["dec_in"].append(u)
+        cache["dec_in"].append(r(u))
         i = next(it)
-        a = np.maximum(conv3x3(u, params[i], params[i + 1]), 0.0)
+        a = np.maximum(conv3x3(r(u), params[i], params[i + 1]), 0.0)
         cache["dec_mid"].append(a)
         i = next(it)
-        h = np.maximum(conv3x3(a, params[i], params[i + 1]), 0.0)
+        h = np.maximum(conv3x3(r(a), params[i], params[i + 1]), 0.0)
         cache["dec_out"].append(h)
     i = next(it)
     cache["head_in"] = h
@@ -173,7 +182,18 @@ def forward(params, x, levels: int = 4):
 
 
 def backward(params, cache, dy, levels: int = 4):
-    """Gradients (list like params) of a loss whose gradient w.r.t. y is dy."""
+    """Gradients (list like params) of a loss whose gradient w.r.t. y is dy.
+    With the forward pass's act_round, the inputs of every 3x3 convolution
+    and the gradients at its output are rounded the same way (the bias
+    gradients sum the unrounded output gradients)."""
+    r = cache.get("act_round") or _ident
+
+    def back3(x, w, dz):
+        # weight and data gradients from the rounded output gradient; the
+        # bias gradient sums it unrounded
+        dx, dw, _ = conv3x3_backward(x, w, r(dz))
+        return dx, dw, dz.sum(axis=(0, 2, 3))
+
     grads = [None] * len(params)
     i = len(params) - 2
     dh, grads[i], grads[i + 1] = conv1x1_backward(cache["head_in"], params[i], dy)
@@ -183,10 +203,10 @@ def backward(params, cache, dy, levels: int = 4):
         pos = levels - 2 - l            # index in the forward decoder lists
         dh = dh * (cache["dec_out"][pos] > 0)
         i -= 2
-        da, grads[i], grads[i + 1] = conv3x3_backward(cache["dec_mid"][pos], params[i], dh)
+        da, grads[i], grads[i + 1] = back3(r(cache["dec_mid"][pos]), params[i], dh)
         da = da * (cache["dec_mid"][pos] > 0)
         i -= 2
-        du, grads[i], grads[i + 1] = conv3x3_backward(cache["dec_in"][pos], params[i], da)
+        du, grads[i], grads[i + 1] = back3(cache["dec_in"][pos], params[i], da)
         c_up = du.shape[1] - cache["enc_out"][l].shape[1]
         dskip[l] = du[:, c_up:]
         dh = upsample2_backward(du[:, :c_up])
@@ -195,10 +215,10 @@ def backward(params, cache, dy, levels: int = 4):
             dh = avgpool2_backward(dh) + dskip[l]
         dh = dh * (cache["enc_out"][l] > 0)
         i -= 2
-        da, grads[i], grads[i + 1] = conv3x3_backward(cache["enc_mid"][l], params[i], dh)
+        da, grads[i], grads[i + 1] = back3(r(cache["enc_mid"][l]), params[i], dh)
         da = da * (cache["enc_mid"][l] > 0)
         i -= 2
-        dh, grads[i], grads[i + 1] = conv3x3_backward(cache["enc_in"][l], params[i], da)
+        dh, grads[i], grads[i + 1] = back3(cache["enc_in"][l], params[i], da)
     return grads
 
 
@@ -206,8 +226,8 @@ def mse(y, target):
     return float(np.mean((y - target) ** 2)), 2.0 * (y - target) / y.size
 
 
-def loss_and_grads(params, x, target, levels: int = 4):
-    y, cache = forward(params, x, levels)
+def loss_and_grads(params, x, target, levels: int = 4, act_round=None):
+    y, cache = forward(params, x, levels, act_round)
     loss, dy = mse(y, target)
     return loss, backward(params, cache, dy, levels), y
 

@@ -880,17 +880,30 @@ __global__ __launch_bounds__(256) void k_rows_inv(
     dft16<1>(a);
     float2* __restrict__ pm = psi + base;
     const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
+    // loads of a batch before its stores (the compiler may not move a load
+    // above a store it cannot show to be elsewhere)
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) {
-      const int v = B * n1 + n2;
-      const float2 pr = Pm[v];
-      const float2 phi = cmul(pr, Or[v]);
-      const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
-      const float2 pn = cadd(pm[v], d);
-      pm[v] = pn;
-      e_d += cabs2(d);
-      e_n += cabs2(pn);
-      oacc[n1] = cadd(oacc[n1], cmulc(pr, pn));
+    for (int b = 0; b < 16; b += 8) {
+      float2 pr[8], ov[8], pv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int v = B * (b + k) + n2;
+        pr[k] = Pm[v];
+        ov[k] = Or[v];
+        pv[k] = pm[v];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int n1 = b + k;
+        const int v = B * n1 + n2;
+        const float2 phi = cmul(pr[k], ov[k]);
+        const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
+        const float2 pn = cadd(pv[k], d);
+        pm[v] = pn;
+        e_d += cabs2(d);
+        e_n += cabs2(pn);
+        oacc[n1] = cadd(oacc[n1], cmulc(pr[k], pn));
+      }
     }
   }
   float2* __restrict__ oj = opart + (size_t)j * FF + (size_t)row * F;

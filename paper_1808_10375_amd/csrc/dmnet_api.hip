@@ -18,9 +18,12 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Conv {
-  int cin, cout, k;
+  int cin, cout, k, level;
   size_t w_off, b_off;  // offsets (in floats) into the parameter vector
 };
+
+// pixels per block of the matrix-core weight gradient (a multiple of 32)
+constexpr int kWgradChunk = 4096;
 
 struct Shape {
   std::vector<Conv> convs;  // parameter order
@@ -43,8 +46,8 @@ Shape make_shape(const dmnet_desc& d) {
   Shape s;
   const int L = d.levels;
   for (int l = 0; l < L; ++l) s.ch.push_back(d.base_ch << l);
-  auto add = [&](int cin, int cout, int k) {
-    Conv c{cin, cout, k, s.n_params, 0};
+  auto add = [&](int cin, int cout, int k, int level) {
+    Conv c{cin, cout, k, level, s.n_params, 0};
     s.n_params += (size_t)cin * cout * k * k;
     c.b_off = s.n_params;
     s.n_params += cout;
@@ -52,15 +55,15 @@ Shape make_shape(const dmnet_desc& d) {
   };
   int prev = 1;
   for (int l = 0; l < L; ++l) {
-    add(prev, s.ch[l], 3);
-    add(s.ch[l], s.ch[l], 3);
+    add(prev, s.ch[l], 3, l);
+    add(s.ch[l], s.ch[l], 3, l);
     prev = s.ch[l];
   }
   for (int l = L - 2; l >= 0; --l) {
-    add(s.ch[l + 1] + s.ch[l], s.ch[l], 3);
-    add(s.ch[l], s.ch[l], 3);
+    add(s.ch[l + 1] + s.ch[l], s.ch[l], 3, l);
+    add(s.ch[l], s.ch[l], 3, l);
   }
-  add(s.ch[0], 2, 1);
+  add(s.ch[0], 2, 1, 0);
   return s;
 }
 
@@ -98,8 +101,14 @@ ActLayout act_layout(const dmnet_desc& d, const Shape& s) {
 }
 
 struct NetLayout {
-  size_t params, wb, grads, m, v, acts, grad_acts, partial, loss, total;
+  size_t params, wb, wbT, grads, m, v, acts, grad_acts, wpart, partial, loss, total;
 };
+
+// chunks of the matrix-core weight gradient of conv c at n samples
+int wgrad_chunks(const dmnet_desc& d, const Conv& c, int n) {
+  const long hw = (long)(d.size >> c.level) * (d.size >> c.level);
+  return (int)((n * hw + kWgradChunk - 1) / kWgradChunk);
+}
 
 constexpr int kMseBlocks = 256;
 
@@ -113,11 +122,17 @@ NetLayout net_layout(const dmnet_desc& d, const Shape& s, const ActLayout& a) {
   };
   L.params = take(s.n_params * 4);
   L.wb = take(s.n_params * 2);
+  L.wbT = take(s.n_params * 2);  // flipped, transposed 3x3 weights (data gradient)
   L.grads = take(s.n_params * 4);
   L.m = take(s.n_params * 4);
   L.v = take(s.n_params * 4);
   L.acts = take(a.total * 4 * d.batch);
   L.grad_acts = take(a.total * 4 * d.batch);
+  size_t wpart = 1;
+  for (const Conv& c : s.convs)
+    if (c.k == 3)
+      wpart = std::max(wpart, (size_t)wgrad_chunks(d, c, d.batch) * c.cout * c.cin * 9);
+  L.wpart = take(wpart * 4);
   L.partial = take(kMseBlocks * 4);
   L.loss = take(4);
   L.total = off;
@@ -139,6 +154,8 @@ struct dmnet {
   float* f(size_t off) { return reinterpret_cast<float*>(ws + off); }
   float* params() { return f(L.params); }
   uint16_t* wb() { return reinterpret_cast<uint16_t*>(ws + L.wb); }
+  uint16_t* wbT() { return reinterpret_cast<uint16_t*>(ws + L.wbT); }
+  bool mfma() const { return !(d.flags & DMNET_FLAG_FP32_WEIGHTS); }
   float* grads() { return f(L.grads); }
   float* act(size_t o) { return f(L.acts) + o; }     // per-sample stride a.total
   float* gact(size_t o) { return f(L.grad_acts) + o; }
@@ -182,6 +199,25 @@ dm_status check(dmnet* n, int count) {
 
 unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
 
+// the flipped, transposed bfloat16 weights of every 3x3 convolution, the A
+// operand of the matrix-core data gradient; redone whenever the weights change
+dm_status refresh_transposed(dmnet* net) {
+  if (!net->mfma()) return DM_OK;
+  for (const Conv& c : net->s.convs) {
+    if (c.k != 3) continue;
+    const long cnt = (long)c.cout * c.cin * 9;
+    hipLaunchKernelGGL(dmn::k_flip_transpose3, dim3(grid_for(cnt)), dim3(256), 0, net->stream,
+                       net->wb() + c.w_off, c.cout, c.cin, net->wbT() + c.w_off);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    net->failed = true;
+    net->err = std::string("k_flip_transpose3: ") + hipGetErrorString(e);
+    return DM_E_HIP;
+  }
+  return DM_OK;
+}
+
 // y = conv(x) (+ ReLU); x, y are per-sample-strided tensors
 dm_status conv_fwd(dmnet* net, const Conv& c, const float* x, long x_ns, float* y, long y_ns,
                    int H, int W, int n, bool relu) {
@@ -190,6 +226,13 @@ dm_status conv_fwd(dmnet* net, const Conv& c, const float* x, long x_ns, float* 
   const uint16_t* wb = net->wb() + c.w_off;
   const float* b = net->params() + c.b_off;
   const int HW = H * W;
+  if (net->mfma() && c.k == 3) {
+    dim3 g((unsigned)(((long)n * HW + 255) / 256), (c.cout + 31) / 32);
+    hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, n,
+                       wb, b, y, c.cout, y_ns, relu ? 1 : 0);
+    NET_LAUNCHED(net, "k_conv3_mfma");
+    return DM_OK;
+  }
   const int bs = std::min(256, HW);
   constexpr int COB = 8;
   dim3 grid((HW + bs - 1) / bs, (c.cout + COB - 1) / COB, n);
@@ -221,6 +264,29 @@ dm_status conv_bwd(dmnet* net, const Conv& c, const float* x, long x_ns, const f
   const uint16_t* wb = net->wb() + c.w_off;
   float* dw = net->grads() + c.w_off;
   float* db = net->grads() + c.b_off;
+  if (net->mfma() && c.k == 3 && (H * W) % 8 == 0) {
+    const int K = c.cin * 9;
+    const int nch = wgrad_chunks(net->d, c, n);
+    float* part = net->f(net->L.wpart);
+    hipLaunchKernelGGL(dmn::k_conv3_wgrad_mfma, dim3((K + 255) / 256, (c.cout + 31) / 32, nch),
+                       dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, c.cout, z_ns, n,
+                       kWgradChunk, part);
+    NET_LAUNCHED(net, "k_conv3_wgrad_mfma");
+    const long cnt = (long)c.cout * K;
+    hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(cnt)), dim3(256), 0, net->stream, part,
+                       nch, cnt, dw);
+    NET_LAUNCHED(net, "k_sum_chunks");
+    hipLaunchKernelGGL(dmn::k_bias_grad, dim3(c.cout), dim3(256), 0, net->stream, dz, z_ns,
+                       H * W, n, db);
+    NET_LAUNCHED(net, "k_bias_grad");
+    if (dx) {
+      dim3 g((unsigned)(((long)n * H * W + 255) / 256), (c.cin + 31) / 32);
+      hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, dz, c.cout, H, W,
+                         z_ns, n, net->wbT() + c.w_off, nullptr, dx, c.cin, dx_ns, 0);
+      NET_LAUNCHED(net, "k_conv3_mfma (data gradient)");
+    }
+    return DM_OK;
+  }
   if (c.k == 3) {
     constexpr int CIB = 4;
     hipLaunchKernelGGL((dmn::k_conv_wgrad<3, CIB>), dim3(c.cout, (c.cin + CIB - 1) / CIB),
@@ -417,7 +483,7 @@ dm_status dmnet_create(dmnet** out, const dmnet_desc* d, void* ws, size_t ws_byt
                      0.f);
   hipLaunchKernelGGL(dmn::k_to_bf16, dim3(grid_for(P)), dim3(256), 0, n->stream, n->params(),
                      n->wb(), P);
-  if (hipGetLastError() != hipSuccess) {
+  if (hipGetLastError() != hipSuccess || refresh_transposed(n) != DM_OK) {
     delete n;
     return DM_E_HIP;
   }
@@ -433,6 +499,7 @@ dm_status dmnet_set_params(dmnet* n, const float* p) {
   hipLaunchKernelGGL(dmn::k_to_bf16, dim3(grid_for(P)), dim3(256), 0, n->stream, n->params(),
                      n->wb(), P);
   NET_LAUNCHED(n, "k_to_bf16");
+  NET_TRY(refresh_transposed(n));
   hipLaunchKernelGGL(dmn::k_fill, dim3(grid_for(P)), dim3(256), 0, n->stream, n->f(n->L.m), P,
                      0.f);
   hipLaunchKernelGGL(dmn::k_fill, dim3(grid_for(P)), dim3(256), 0, n->stream, n->f(n->L.v), P,
@@ -489,7 +556,7 @@ dm_status dmnet_train_step(dmnet* n, const float* x, const float* target, int32_
                      n->f(n->L.m), n->f(n->L.v), n->grads(), n->wb(), P, n->d.lr, n->d.beta1,
                      n->d.beta2, n->d.eps, c1, c2);
   NET_LAUNCHED(n, "k_adam");
-  return DM_OK;
+  return refresh_transposed(n);
 }
 
 dm_status dmnet_preprocess(dmnet* n, const float* I, int32_t count, int32_t frame, float* x) {

@@ -137,6 +137,219 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
+// 3x3 convolutions on the matrix cores (v_mfma_f32_16x16x32_bf16): implicit
+// GEMMs with bfloat16 operands and float32 accumulation.  Pixels of all
+// samples form one index P = sample * H*W + p.  Operand layout (one wave):
+// A (16 x 32): lane l holds row l%16, k = 8*(l/16) + e; B (32 x 16): lane l
+// holds column l%16, k = 8*(l/16) + e; C: lane l holds column l%16, rows
+// 4*(l/16) + r.
+// ---------------------------------------------------------------------------
+typedef __bf16 nb_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float nb_f32x4 __attribute__((ext_vector_type(4)));
+typedef short nb_s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ nb_f32x4 nb_mma(nb_s16x8 a, nb_s16x8 b, nb_f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(nb_bf16x8, a),
+                                                 __builtin_bit_cast(nb_bf16x8, b), c, 0, 0, 0);
+}
+
+// value of the 3x3 im2col matrix at (k = c*9 + t, pixel P), zero outside
+__device__ __forceinline__ float im2col3(const float* __restrict__ x, long x_ns, int xc, int H,
+                                         int W, int sample, int i, int j, int k, int K) {
+  if (k >= K) return 0.f;
+  const int c = k / 9, t = k - 9 * c;
+  const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
+  if ((unsigned)ii >= (unsigned)H || (unsigned)jj >= (unsigned)W) return 0.f;
+  return x[(long)sample * x_ns + ((long)c * H + ii) * W + jj];
+}
+
+// y[o][P] = b[o] + sum_k A[o][k] im2col(x)[k][P]  (K = xc * 9), optional ReLU.
+// A: bfloat16 [yc][xc * 9].  With A = the flipped, transposed weights and
+// x = the output gradient this is the data gradient.
+// Block: 4 waves; tile 32 output channels x 256 pixels (64 per wave).
+// grid (ceil(n H W / 256), ceil(yc / 32))
+__global__ __launch_bounds__(256) void k_conv3_mfma(const float* __restrict__ x, int xc, int H,
+                                                    int W, long x_ns, int n,
+                                                    const uint16_t* __restrict__ A,
+                                                    const float* __restrict__ bias,
+                                                    float* __restrict__ y, int yc, long y_ns,
+                                                    int relu) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int HW = H * W, NP = n * HW, K = xc * 9;
+  const int o0 = blockIdx.y * 32;
+  const int pw = blockIdx.x * 256 + wave * 64;  // first pixel of this wave
+  // the four pixels this lane feeds to the B operands
+  int smp[4], pi[4], pj[4];
+  bool pok[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int P = pw + 16 * ct + (lane & 15);
+    pok[ct] = P < NP;
+    const int Pc = pok[ct] ? P : 0;
+    smp[ct] = Pc / HW;
+    const int p = Pc - smp[ct] * HW;
+    pi[ct] = p / W;
+    pj[ct] = p - pi[ct] * W;
+  }
+  nb_f32x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kb = k0 + 8 * (lane >> 4);
+    nb_s16x8 a[2], b[4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int o = o0 + 16 * rt + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        a[rt][e] = (o < yc && kb + e < K) ? (short)A[(long)o * K + kb + e] : (short)0;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float v = pok[ct] ? im2col3(x, x_ns, xc, H, W, smp[ct], pi[ct], pj[ct], kb + e, K)
+                                : 0.f;
+        b[ct][e] = (short)f_to_bf16_bits(v);
+      }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_mma(a[rt], b[ct], acc[rt][ct]);
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    if (!pok[ct]) continue;
+    const int p = pi[ct] * W + pj[ct];
+    float* __restrict__ yn = y + (long)smp[ct] * y_ns;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + 16 * rt + 4 * (lane >> 4) + r;
+        if (o < yc) {
+          float v = acc[rt][ct][r] + (bias ? bias[o] : 0.f);
+          yn[(long)o * HW + p] = relu ? fmaxf(v, 0.f) : v;
+        }
+      }
+  }
+}
+
+// Weight gradient of a 3x3 convolution over one chunk of pixels:
+//   part[chunk][o][k] = sum_{P in chunk} dz[o][P] im2col(x)[k][P]
+// GEMM rows o (zc), columns k (xc * 9), reduction over P in steps of 32.
+// H*W must be a multiple of 8 (8 consecutive pixels stay in one sample).
+// Block: 4 waves; tile 32 o x 256 k (64 per wave).
+// grid (ceil(K / 256), ceil(zc / 32), n_chunks)
+__global__ __launch_bounds__(256) void k_conv3_wgrad_mfma(
+    const float* __restrict__ x, int xc, int H, int W, long x_ns, const float* __restrict__ dz,
+    int zc, long z_ns, int n, int chunk, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int HW = H * W, NP = n * HW, K = xc * 9;
+  const int o0 = blockIdx.y * 32;
+  const int kw = blockIdx.x * 256 + wave * 64;
+  const int P0 = blockIdx.z * chunk, P1 = min(NP, P0 + chunk);
+  nb_f32x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int Ps = P0; Ps < P1; Ps += 32) {
+    const int Pb = Ps + 8 * (lane >> 4);  // 8 consecutive pixels of one sample
+    const bool in = Pb < P1;
+    const int sample = in ? Pb / HW : 0;
+    const int p = in ? Pb - sample * HW : 0;
+    nb_s16x8 a[2], b[4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int o = o0 + 16 * rt + (lane & 15);
+      const float* __restrict__ src = dz + (long)sample * z_ns + (long)o * HW + p;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        a[rt][e] = (short)f_to_bf16_bits((in && o < zc && Pb + e < P1) ? src[e] : 0.f);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int k = kw + 16 * ct + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float v = 0.f;
+        if (in && Pb + e < P1) {
+          const int pe = p + e;
+          const int i = pe / W, j = pe - (pe / W) * W;
+          v = im2col3(x, x_ns, xc, H, W, sample, i, j, k, K);
+        }
+        b[ct][e] = (short)f_to_bf16_bits(v);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_mma(a[rt], b[ct], acc[rt][ct]);
+  }
+  float* __restrict__ pc = part + (long)blockIdx.z * zc * K;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int k = kw + 16 * ct + (lane & 15);
+      if (k >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + 16 * rt + 4 * (lane >> 4) + r;
+        if (o < zc) pc[(long)o * K + k] = acc[rt][ct][r];
+      }
+    }
+}
+
+// dw[e] = sum over chunks of part[chunk][e], in chunk order
+__global__ void k_sum_chunks(const float* __restrict__ part, int n_chunks, long count,
+                             float* __restrict__ dw) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < n_chunks; ++c) s += part[(long)c * count + e];
+    dw[e] = s;
+  }
+}
+
+// db[o] = sum over samples and pixels of dz[o]; one block per o, the 256
+// per-thread sums added in thread order
+__global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dz, long z_ns,
+                                                   int HW, int n, float* __restrict__ db) {
+  __shared__ float red[256];
+  const int o = blockIdx.x;
+  float s = 0.f;
+  for (int P = threadIdx.x; P < n * HW; P += 256) {
+    const int sample = P / HW, p = P - sample * HW;
+    s += dz[(long)sample * z_ns + (long)o * HW + p];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < 256; ++i) t += red[i];
+    db[o] = t;
+  }
+}
+
+// wT[c][o][8 - t] = w[o][c][t]: the weights of the data gradient as a GEMM
+// operand [xc][yc * 9]
+__global__ void k_flip_transpose3(const uint16_t* __restrict__ w, int yc, int xc,
+                                  uint16_t* __restrict__ wT) {
+  const long total = (long)yc * xc * 9;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(e % 9);
+    const long oc = e / 9;
+    const int c = (int)(oc % xc), o = (int)(oc / xc);
+    wT[((long)c * yc + o) * 9 + (8 - t)] = w[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // elementwise pieces; grid-stride loops over n * C * H * W
 // ---------------------------------------------------------------------------
 // dst = 2x2 average of src (C channels, src H x W)

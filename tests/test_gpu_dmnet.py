@@ -1,11 +1,11 @@
 """GPU parity of the warm-start network and stitch against the FP64 oracles.
 
-Gates: with float32 weights the forward output and every parameter gradient
-match the FP64 network oracle to 1e-4 relative L2; with bfloat16 weights
-they match the oracle evaluated at the same rounded weights to 1e-4, and
-they differ from the unrounded float64 network's by exactly what the oracle
-itself shows the rounding of the weights to cause (1.5e-2 on the test
-network).  Adam's update, the input map and the
+Gates: with float32 weights and activations the forward output and every
+parameter gradient match the FP64 network oracle to 1e-4 relative L2; in the
+bfloat16 mode (3x3 convolutions on the matrix cores with bfloat16 weights and
+activations) they match the oracle run with the same roundings to 1e-5 at
+sizes where no rounding flips, and at the full network size stay within a
+quarter of the roundings' own effect, which the oracle measures.  Adam's update, the input map and the
 patch map are checked against their oracle forms; the warm-start stitch
 against the oracle's object update (Eq. 5) on exit waves P * patch."""
 import numpy as np
@@ -73,23 +73,59 @@ def test_forward_and_gradients_fp32_weights(n, size, c0, levels):
     assert per_layer_worst(g, g_ref, c0, levels) <= 1e-4
 
 
-def test_gradients_bf16_weights():
-    n, size, c0, levels = 2, 16, 4, 3
-    params, x, target = case(21, n, size, c0, levels)
+def bf16_runs(n, size, c0, levels):
+    """GPU forward/loss/gradient in the bfloat16 mode, the oracle run with the
+    same roundings, and the unrounded FP64 network."""
+    params, x, target = case(21 + c0, n, size, c0, levels)
     m = make_net(n, size, c0, levels, fp32w=False)
     m.set_params(net.flatten(params))
+    y = m.forward(to_dev(x)).cpu().numpy()
     loss, g = m.loss_grad(to_dev(x), to_dev(target))
-    g = g.cpu().numpy()
-    rounded = [net.bf16_round(p) for p in params]
-    _, g_round, _ = net.loss_and_grads(rounded, x, target, levels)
-    _, g_exact, _ = net.loss_and_grads(params, x, target, levels)
-    assert rel(g, net.flatten(g_round)) <= 1e-4
-    # against the unrounded float64 network the gradient differs by the
-    # effect of rounding the weights to bfloat16, which the oracle measures
-    # by itself; the GPU adds nothing to it
-    q = rel(net.flatten(g_round), net.flatten(g_exact))
-    print(f"bf16 weight rounding moves the gradient by {q:.3e} (rel L2)")
-    assert abs(rel(g, net.flatten(g_exact)) - q) <= 1e-4
+    # weights are rounded to bfloat16, biases stay float32
+    rounded = [net.bf16_round(p) if i % 2 == 0 else p for i, p in enumerate(params)]
+    l_emu, g_emu, y_emu = net.loss_and_grads(rounded, x, target, levels,
+                                             act_round=net.bf16_round)
+    _, g_exact, y_exact = net.loss_and_grads(params, x, target, levels)
+    return (y, loss, g.cpu().numpy()), (y_emu, l_emu, net.flatten(g_emu)), \
+        (y_exact, net.flatten(g_exact))
+
+
+@pytest.mark.parametrize("n,size,c0,levels", [(2, 16, 4, 3), (3, 24, 8, 2), (1, 16, 40, 3),
+                                              (2, 8, 96, 2)])
+def test_matrix_core_convolutions_match_bf16_emulation(n, size, c0, levels):
+    """bfloat16 mode: 3x3 convolutions on the matrix cores with bfloat16
+    weights and activations.  Against the oracle run with the same roundings
+    (weights, every 3x3 input and output gradient) the forward output, loss
+    and gradient agree to 1e-5: at these sizes the float32-versus-float64
+    sums (about 1e-7) flip no bfloat16 rounding, while a rounding left out on
+    either side moves the result by about 1e-3.  The last two cases use
+    40 to 288 channels, so several channel tiles (one of them partial) and
+    long reductions are covered."""
+    (y, loss, g), (y_emu, l_emu, g_emu), (y_ex, g_ex) = bf16_runs(n, size, c0, levels)
+    r_y, r_g = rel(y, y_emu), rel(g, g_emu)
+    print(f"vs emulation: y {r_y:.2e} grad {r_g:.2e}; bf16 roundings move the "
+          f"gradient by {rel(g_emu, g_ex):.3e}; GPU vs FP64 {rel(g, g_ex):.3e}")
+    assert r_y <= 1e-5 and abs(loss - l_emu) <= 1e-5 * l_emu
+    assert r_g <= 1e-5
+
+
+def test_full_size_bf16_network_within_rounding_noise():
+    """The 4-level 32-64-128-256 network on one 64 x 64 input in the bfloat16
+    mode.  At this depth and width a float32-level difference in the sums
+    flips some bfloat16 roundings and the flips compound from layer to layer
+    (the oracle moves its output by about 1e-2 when every convolution output
+    is perturbed by 1e-7 relative), so element-wise agreement with the
+    emulation is not defined here.  The check: the GPU lies well inside the
+    roundings' own noise -- its distance to the emulation is at most a
+    quarter of the distance between the emulation and the unrounded FP64
+    network, for the output and for the gradient."""
+    (y, loss, g), (y_emu, l_emu, g_emu), (y_ex, g_ex) = bf16_runs(1, 64, 32, 4)
+    q_y, q_g = rel(y_emu, y_ex), rel(g_emu, g_ex)
+    r_y, r_g = rel(y, y_emu), rel(g, g_emu)
+    print(f"vs emulation: y {r_y:.2e} grad {r_g:.2e}; roundings' own effect: y {q_y:.2e} "
+          f"grad {q_g:.2e}; GPU vs FP64: y {rel(y, y_ex):.2e} grad {rel(g, g_ex):.2e}")
+    assert r_y <= 0.25 * q_y and r_g <= 0.25 * q_g
+    assert abs(loss - l_emu) <= 0.01 * l_emu
 
 
 def test_full_size_network_one_sample():

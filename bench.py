@@ -57,9 +57,10 @@ def measured_traffic(launch_key: str, kernel: str):
 # rocprofv3 name of the view kernel of each view path at frame size f
 def view_kernel_name(view_path: int, f: int) -> str:
     return {0: f"k_fourier_fused<{f}, 1>", 1: f"k_rows_fwd<{f}>",
-            2: f"k_fourier_stream<{f}, true, false>",
-            3: f"k_fourier_stream<{f}, false, false>",
-            4: f"k_fourier_stream<{f}, true, true>"}[view_path]
+            2: f"k_fourier_stream<{f}, 1, true, false>",
+            3: f"k_fourier_stream<{f}, 1, false, false>",
+            4: f"k_fourier_stream<{f}, 1, true, true>",
+            5: f"k_fourier_stream<{f}, {2 if f >= 32 else 1}, true, true>"}[view_path]
 
 
 def views_alg_bytes(n, m, f):
@@ -228,7 +229,7 @@ def main():
                     help="skip the batched-scans (and other forms') measurements")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="transform form of the headline run (bf16x3: F = 128 only)")
-    ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3, 4, 5],
                     help="override the library's default view kernel (dm_tuning.view_path)")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")

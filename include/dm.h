@@ -136,6 +136,11 @@ typedef struct {
                                       right after each inverse transform (the
                                       updated spectra make one trip through
                                       the slot instead of two)               */
+#define DM_VIEWS_STREAMED_WIDE 5   /* DM_VIEWS_STREAMED_MERGED with half the
+                                      threads, each running two columns of
+                                      the transform (F >= 32; one at F = 16):
+                                      twice the registers per thread keep the
+                                      modulus scale out of the slot          */
 
 /* Launch shapes chosen per context (dm_set_tuning / dm_autotune).  They
  * change the speed of an iteration and the summation order of the probe

@@ -627,18 +627,23 @@ dm_status launch_views_mfma(dm_ctx* c) {
 template <int F>
 dm_status launch_views_streamed(dm_ctx* c, int vp) {
   const int grid = std::min(c->total_views, c->stream_slots);
+  constexpr int V2 = (F >= 32) ? 2 : 1;
   if (vp == DM_VIEWS_STREAMED)
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true, false>), dim3(grid), dim3(F * F / 16), 0,
-                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, true, false>), dim3(grid), dim3(F * F / 16),
+                       0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
   else if (vp == DM_VIEWS_STREAMED_CACHED)
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, false, false>), dim3(grid), dim3(F * F / 16), 0,
-                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, false, false>), dim3(grid), dim3(F * F / 16),
+                       0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+                       c->vscr());
+  else if (vp == DM_VIEWS_STREAMED_MERGED)
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, true, true>), dim3(grid), dim3(F * F / 16),
+                       0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
   else
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, true, true>), dim3(grid), dim3(F * F / 16), 0,
-                       c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
-                       c->vscr());
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, V2, true, true>), dim3(grid),
+                       dim3(F * F / (16 * V2)), 0, c->stream, c->scan_dev(), c->vmap(),
+                       c->total_views, c->tw(), c->M, c->vscr());
   DM_LAUNCHED(c, "k_fourier_stream");
   return DM_OK;
 }
@@ -966,7 +971,7 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     c->err = "probe_chunks out of range";
     return DM_E_ARG;
   }
-  if (t.reserved != 0 || t.view_path < DM_VIEWS_FUSED || t.view_path > DM_VIEWS_STREAMED_MERGED) {
+  if (t.reserved != 0 || t.view_path < DM_VIEWS_FUSED || t.view_path > DM_VIEWS_STREAMED_WIDE) {
     c->err = "bad tuning fields";
     return DM_E_ARG;
   }
@@ -1268,7 +1273,7 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   const int chunk_opts[3] = {std::max(1, base.probe_chunks / 2), base.probe_chunks,
                              std::min(DM_MAX_PROBE_CHUNKS, base.probe_chunks * 2)};
   const bool have_spec = c->scans[0].L.tspec != 0 && !c->bf16x3();
-  for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_MERGED; ++mp) {
+  for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_WIDE; ++mp) {
     if (c->bf16x3() && mp != DM_VIEWS_FUSED) continue;
     if (mp == DM_VIEWS_THREE_KERNEL && !have_spec) continue;
     if (mp != DM_VIEWS_THREE_KERNEL && c->F > 128) continue;

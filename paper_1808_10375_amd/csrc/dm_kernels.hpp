@@ -496,39 +496,55 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
 // what it wrote) and walks views b, b + G, ... of the XCD-interleaved order.
 //   pass 1  per mode: Z = 2 P O - psi, forward DFT, mode sum S += |Z~|^2,
 //           Z~ -> scratch
-//   scale   g = sqrt(I / S) / F^2 (definition of F_c), kept in registers
-//   pass 2  per mode: Z~ from scratch, times g, inverse DFT, Z' -> scratch
-//   pass 3  per mode: Z' from scratch, psi' = psi + beta (Z' - P O)
-//           (Eq. 3), object numerator sum_k conj(P_k) psi'_k in registers
-// Every mode is transformed twice (no recomputation), no transform runs
-// while the object numerator is live, and psi is read twice and written
-// once with the non-temporal hint (NT) so the probe and the object stay in
-// L2; the slot's scratch is rewritten view after view and stays in cache.
+//   scale   g = sqrt(I / S) / F^2 (definition of F_c)
+//   pass 2  per mode, last mode first (in the merged form with V = 1 its
+//           spectrum never leaves the registers): Z~ from scratch, times g, inverse DFT; with MERGE the
+//           view update psi' = psi + beta (Z' - P O) (Eq. 3) and the object
+//           numerator sum_k conj(P_k) psi'_k follow at once, otherwise Z'
+//           goes back to scratch and
+//   pass 3  per mode: Z' from scratch, the view update and the numerator
+//           (no transform runs while the numerator is live)
+// Every mode is transformed twice (no recomputation); psi is read twice and
+// written once, with the non-temporal hint (NT) so the probe and the object
+// stay in L2.  A thread runs V virtual threads of the transform (F*F/(16 V)
+// threads).  With V = 1 (128 registers a thread) the merged form parks the
+// scale to make room for the numerator: the rows that fit beside the
+// exchange buffer in LDS, the rest in the slot; with V = 2 (256 registers)
+// the scale and the numerator both stay in registers.
 // ---------------------------------------------------------------------------
-template <int F, bool NT_HINT, bool MERGE>
-__global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
+template <int F, int V, bool NT_HINT, bool MERGE>
+__global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
     const float2* __restrict__ tw, int M, float2* __restrict__ vscr) {
   constexpr int B = F / 16;
-  constexpr int NT = F * B;
+  constexpr int NT = F * B / V;  // threads
+  constexpr int GS = B / V;      // row-group step between a thread's virtual threads
   constexpr int LD = F + 1;
   constexpr int FF = F * F;
+  constexpr bool kPark = MERGE && V == 1;
+  constexpr bool kKeep = kPark;  // keeps the last spectrum in registers
+  // scale rows parked in LDS: as many as fit in 160 KB beside the rest
+  constexpr int kLdsFixed = F * LD * 8 + 2 * ((NT + 63) / 64) * 4 + F * 8 + 256;
+  constexpr int kLdsRows = !kPark ? 0
+                           : ((163840 - kLdsFixed) / (NT * 4) < 16 ? (163840 - kLdsFixed) / (NT * 4)
+                                                                   : 16);
   __shared__ float2 buf[F * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
   __shared__ float2 twl[F];
+  __shared__ float gl[kLdsRows > 0 ? kLdsRows * NT : 1];
 
   const int t = threadIdx.x;
   for (int i = t; i < F; i += NT) twl[i] = tw[i];
   __syncthreads();
   const int c = t % F;
   const int g0 = wave_uniform_div<F>(t);
-  // slot: the spectra [M][16][NT] complex, then the modulus scale [16][NT]
+  // slot: the spectra [M][V][16][NT] complex, then the modulus scale [16][NT]
   const size_t slot_words = (size_t)M * FF * 2 + FF;
   float* const slot = reinterpret_cast<float*>(vscr) + (size_t)blockIdx.x * slot_words;
   const rsrc_t rs = make_rsrc(slot, (uint32_t)(slot_words * 4));
   const int sG = M * FF * 8;  // byte offset of the scale in the slot
-  const int vS = t * 8;  // scratch: [mode][r][thread]
-  auto rowS = [&](int m, int r) { return (m * 16 + r) * NT * 8; };
+  const int vS = t * 8;
+  auto rowS = [&](int m, int v, int r) { return ((m * V + v) * 16 + r) * NT * 8; };
 
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int2 vm = vmap[xcd_slot(item, total)];
@@ -540,41 +556,51 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
     const rsrc_t rpsi = make_rsrc(sc.psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
     const rsrc_t rP = make_rsrc(sc.P, (uint32_t)(M * FF * 8));
     const rsrc_t rO = make_rsrc(sc.O, (uint32_t)((size_t)H * W * 8));
+    // per-lane offsets of the first virtual thread (row g0, column c); rows
+    // of the other virtual threads differ by wave-uniform offsets
     const int vF = (g0 * F + c) * 8;
     const int vO = (g0 * W + c) * 8;
     const int sO = (y0 * W + x0) * 8;
-    auto rowF = [&](int u1) { return B * u1 * F * 8; };
-    auto rowO = [&](int u1) { return B * u1 * W * 8; };
+    auto rowF = [&](int v, int u1) { return (B * u1 + v * GS) * F * 8; };
+    auto rowO = [&](int v, int u1) { return (B * u1 + v * GS) * W * 8; };
     auto ld_psi = [&](int off) { return NT_HINT ? bload2_nt(rpsi, vF, off) : bload2(rpsi, vF, off); };
 
-    float2 a[1][16];
-    float S[16];
+    float2 a[V][16];
+    float S[V][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) S[r] = 0.f;
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S[v][r] = 0.f;
     // ---- pass 1 (loads in batches, all of a batch issued before its use)
     for (int m = 0; m < M; ++m) {
       const int sm = m * FF * 8;
 #pragma unroll
-      for (int b = 0; b < 16; b += 8) {
-        float2 ps[8], pp[8], oo[8];
+      for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          ps[k] = ld_psi(sm + rowF(b + k));
-          pp[k] = bload2(rP, vF, sm + rowF(b + k));
-          oo[k] = bload2(rO, vO, sO + rowO(b + k));
+        for (int b = 0; b < 16; b += 8) {
+          float2 ps[8], pp[8], oo[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            ps[k] = ld_psi(sm + rowF(v, b + k));
+            pp[k] = bload2(rP, vF, sm + rowF(v, b + k));
+            oo[k] = bload2(rO, vO, sO + rowO(v, b + k));
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const float2 phi = cmul(pp[k], oo[k]);
+            a[v][b + k] = make_float2(2.f * phi.x - ps[k].x, 2.f * phi.y - ps[k].y);
+          }
         }
+      Frame2D<F, -1, V>::fwd(a, buf, twl, c, g0);
+      // merged form: the last mode's spectrum stays in registers for pass 2
+      const bool keep = kKeep && (m == M - 1);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const float2 phi = cmul(pp[k], oo[k]);
-          a[0][b + k] = make_float2(2.f * phi.x - ps[k].x, 2.f * phi.y - ps[k].y);
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          S[v][r] += cabs2(a[v][r]);
+          if (!keep) bstore2(rs, a[v][r], vS, rowS(m, v, r));
         }
-      }
-      Frame2D<F, -1, 1>::fwd(a, buf, twl, c, g0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        S[r] += cabs2(a[0][r]);
-        bstore2(rs, a[0][r], vS, rowS(m, r));
-      }
     }
     // ---- modulus scale from I staged through LDS (padded rows)
     {
@@ -585,90 +611,110 @@ __global__ __launch_bounds__(F * F / 16) void k_fourier_stream(
       __syncthreads();
       const float inv_ff = 1.0f / (float)FF;
 #pragma unroll
-      for (int i = 0; i < 16 / B; ++i)
+      for (int v = 0; v < V; ++v) {
+        const int g = g0 + v * GS;
 #pragma unroll
-        for (int l2 = 0; l2 < B; ++l2) {
-          const int r = i * B + l2;
-          const int l = (g0 + B * i) + 16 * l2;
-          const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
-          const float sv = S[r];
-          S[r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
-        }
+        for (int i = 0; i < 16 / B; ++i)
+#pragma unroll
+          for (int l2 = 0; l2 < B; ++l2) {
+            const int r = i * B + l2;
+            const int l = (g + B * i) + 16 * l2;
+            const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
+            const float sv = S[v][r];
+            S[v][r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+          }
+      }
       __syncthreads();  // bI aliases the exchange buffer
     }
-    float2 oacc[16];
+    float2 oacc[V][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) oacc[v][r] = make_float2(0.f, 0.f);
     float e_d = 0.f, e_n = 0.f;
     // The stores of psi' may alias later loads as far as the compiler knows,
     // so no load is moved above a store: every batch issues all of its loads
     // first, then computes and stores.
     constexpr int KB = 4;  // elements per batch
-    // view update of mode m from Z' (zp(k) gives element b + k)
+    // view update of mode m from Z' (zp(v, u) gives element u of virtual thread v)
     auto update = [&](int m, auto zp_of) {
       const int sm = m * FF * 8;
 #pragma unroll
-      for (int b = 0; b < 16; b += KB) {
-        float2 zp[KB], pr[KB], ov[KB], ps[KB];
+      for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-          zp[k] = zp_of(b + k);
-          pr[k] = bload2(rP, vF, sm + rowF(b + k));
-          ov[k] = bload2(rO, vO, sO + rowO(b + k));
-          ps[k] = ld_psi(sm + rowF(b + k));
-        }
+        for (int b = 0; b < 16; b += KB) {
+          float2 zp[KB], pr[KB], ov[KB], ps[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-          const float2 phi = cmul(pr[k], ov[k]);
-          const float2 d = make_float2(beta * (zp[k].x - phi.x), beta * (zp[k].y - phi.y));
-          const float2 pn = cadd(ps[k], d);
-          if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(b + k));
-          else bstore2(rpsi, pn, vF, sm + rowF(b + k));
-          e_d += cabs2(d);
-          e_n += cabs2(pn);
-          oacc[b + k] = cadd(oacc[b + k], cmulc(pr[k], pn));
+          for (int k = 0; k < KB; ++k) {
+            zp[k] = zp_of(v, b + k);
+            pr[k] = bload2(rP, vF, sm + rowF(v, b + k));
+            ov[k] = bload2(rO, vO, sO + rowO(v, b + k));
+            ps[k] = ld_psi(sm + rowF(v, b + k));
+          }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            const float2 phi = cmul(pr[k], ov[k]);
+            const float2 d = make_float2(beta * (zp[k].x - phi.x), beta * (zp[k].y - phi.y));
+            const float2 pn = cadd(ps[k], d);
+            if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(v, b + k));
+            else bstore2(rpsi, pn, vF, sm + rowF(v, b + k));
+            e_d += cabs2(d);
+            e_n += cabs2(pn);
+            oacc[v][b + k] = cadd(oacc[v][b + k], cmulc(pr[k], pn));
+          }
         }
-      }
     };
-    // ---- pass 2: scaled spectra back to the spatial domain; with MERGE the
-    // view update follows each inverse transform directly (the object
-    // numerator stays live through the transforms, and the scale is parked
-    // in the slot to make room for it), otherwise Z' goes back to the slot
-    // and pass 3 updates
-    if constexpr (MERGE) {
+    // ---- pass 2: scaled spectra back to the spatial domain
+    if constexpr (kPark) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[r]), rs, t * 4,
-                                              sG + r * NT * 4, 0);
-    }
-    for (int m = 0; m < M; ++m) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) a[0][r] = bload2(rs, vS, rowS(m, r));
-      if constexpr (MERGE) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) a[0][r] = cscale(a[0][r], bload1(rs, t * 4, sG + r * NT * 4));
-      } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) a[0][r] = cscale(a[0][r], S[r]);
+      for (int r = 0; r < 16; ++r) {
+        if (r < kLdsRows) gl[r * NT + t] = S[0][r];
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S[0][r]), rs, t * 4,
+                                                sG + r * NT * 4, 0);
       }
-      Frame2D<F, 1, 1>::inv(a, buf, twl, c, g0);
-      if constexpr (MERGE) {
-        update(m, [&](int u) { return a[0][u]; });
+    }
+    for (int m = M - 1; m >= 0; --m) {
+      if (!kKeep || m != M - 1) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) a[v][r] = bload2(rs, vS, rowS(m, v, r));
+      }
+      if constexpr (kPark) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          a[0][r] = cscale(a[0][r], r < kLdsRows ? gl[r * NT + t]
+                                                 : bload1(rs, t * 4, sG + r * NT * 4));
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) bstore2(rs, a[0][r], vS, rowS(m, r));
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) a[v][r] = cscale(a[v][r], S[v][r]);
+      }
+      Frame2D<F, 1, V>::inv(a, buf, twl, c, g0);
+      if constexpr (MERGE) {
+        update(m, [&](int v, int u) { return a[v][u]; });
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) bstore2(rs, a[v][r], vS, rowS(m, v, r));
       }
     }
     // ---- pass 3: view update and the object numerator
     if constexpr (!MERGE) {
-      for (int m = 0; m < M; ++m) update(m, [&](int u) { return bload2(rs, vS, rowS(m, u)); });
+      for (int m = 0; m < M; ++m)
+        update(m, [&](int v, int u) { return bload2(rs, vS, rowS(m, v, u)); });
     }
     const rsrc_t ropart = make_rsrc(sc.opart + (size_t)j * FF, (uint32_t)(FF * 8));
 #pragma unroll
-    for (int u1 = 0; u1 < 16; ++u1) {
-      if (NT_HINT) bstore2_nt(ropart, oacc[u1], vF, rowF(u1));
-      else bstore2(ropart, oacc[u1], vF, rowF(u1));
-    }
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int u1 = 0; u1 < 16; ++u1) {
+        if (NT_HINT) bstore2_nt(ropart, oacc[v][u1], vF, rowF(v, u1));
+        else bstore2(ropart, oacc[v][u1], vF, rowF(v, u1));
+      }
     block_sum2<NT>(e_d, e_n, red);
     if (t == 0) {
       sc.err_psi[2 * j] = e_d;
@@ -1044,7 +1090,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
 // Probe update (Eq. 4), stage 1: per chunk of views (consecutive in the
 // spatial view order) and block of 256 probe pixels,
 // sum_j conj(O'[win_j]) psi'_{j,k} for every mode and sum_j |O'[win_j]|^2.
-// Modes in groups of 8 held in registers; two views' loads in flight.
+// Modes in groups of 8 held in registers; four views' loads in flight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict__ scans,
                                                        const int2* __restrict__ cmap, int M,
@@ -1069,11 +1115,13 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = make_float2(0.f, 0.f);
     float den = 0.f;
+    // kVU views per step, all of their loads issued before their use
+    constexpr int kVU = 4;
     int i = j0;
-    for (; i + 2 <= j1; i += 2) {
-      float2 o[2], w[2][8];
+    for (; i + kVU <= j1; i += kVU) {
+      float2 o[kVU], w[kVU][8];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < kVU; ++k) {
         const int jv = order[i + k];
         const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
         o[k] = O[(size_t)(yj + u) * W + xj + v];
@@ -1083,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
           w[k][q] = (mg + q < M) ? pj[(size_t)q * FF] : make_float2(0.f, 0.f);
       }
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < kVU; ++k) {
         den += cabs2(o[k]);
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmulc(o[k], w[k][q]));

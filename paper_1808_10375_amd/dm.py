@@ -35,6 +35,7 @@ DM_VIEWS_THREE_KERNEL = 1
 DM_VIEWS_STREAMED = 2
 DM_VIEWS_STREAMED_CACHED = 3
 DM_VIEWS_STREAMED_MERGED = 4
+DM_VIEWS_STREAMED_WIDE = 5
 DM_MAX_MODES = 16
 DM_MAX_PROBE_CHUNKS = 64
 PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]

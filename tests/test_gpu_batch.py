@@ -127,7 +127,8 @@ def test_graph_replays_equal_eager_launches():
 
 
 @pytest.mark.parametrize("tile,chunks,view_path", [(32, 16, 0), (16, 3, 0), (32, 64, 1),
-                                                   (16, 16, 2), (32, 8, 3), (16, 8, 4)])
+                                                   (16, 16, 2), (32, 8, 3), (16, 8, 4),
+                                                   (32, 16, 5)])
 def test_tunings_keep_parity(tile, chunks, view_path):
     _torch()
     from paper_1808_10375_amd import dm

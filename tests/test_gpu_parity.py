@@ -119,14 +119,15 @@ def test_one_step_random_state(seed, n, f, m, h, w):
     one_step_case(synth.random_case(seed, n, f, m, h, w))
 
 
-@pytest.mark.parametrize("view_path", [2, 3, 4])
+@pytest.mark.parametrize("view_path", [2, 3, 4, 5])
 @pytest.mark.parametrize("seed,n,f,m,h,w", [(1, 37, 16, 1, 70, 53), (2, 37, 32, 2, 100, 90),
                                             (4, 41, 64, 3, 200, 170),
                                             (5, 19, 128, 5, 300, 270),
                                             (7, 11, 64, 16, 130, 130)])
 def test_one_step_streamed_path(seed, n, f, m, h, w, view_path):
-    """The persistent streamed view kernel, with and without the
-    non-temporal hint on psi."""
+    """The persistent streamed view kernel: with and without the
+    non-temporal hint on psi, with the update merged into the inverse pass,
+    and with two transform columns per thread."""
     say(f"case streamed view_path={view_path} seed={seed} N={n} F={f} M={m} obj={h}x{w}")
     one_step_case(synth.random_case(seed, n, f, m, h, w), view_path=view_path)
 
@@ -255,7 +256,7 @@ def test_nan_intensity_rejected():
     assert ex.value.status == dm.DM_E_ARG
 
 
-@pytest.mark.parametrize("view_path", [0, 2, 4])
+@pytest.mark.parametrize("view_path", [0, 2, 4, 5])
 def test_multimode_2500x5_128_full_size_one_step(view_path):
     """The 2500-view, 5-mode, 128x128 scan at full size, from its initial
     views, through the fused and the streamed view kernels."""

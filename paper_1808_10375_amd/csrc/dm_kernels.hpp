@@ -969,10 +969,22 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 // per-view numerators sum_k conj(P_k) psi'_k and the mode power
 // D = sum_k |P_k|^2 (the normaliser, in double).  The block has G groups of
 // 256 threads; group q takes the views e = q, q + G, ... of the tile's list
-// (ascending), two at a time, so G * 2 views are in flight; the G partial
+// (ascending), U at a time (8 for 16 x 16 tiles, 2 for 32 x 32), so G * U
+// views are in flight; the G partial
 // sums of each pixel are then added in group order through LDS.  The order of
 // every sum is fixed, so results are bitwise reproducible.
 // ---------------------------------------------------------------------------
+// Workgroup b runs on XCD b mod 8.  Map the blocks so that each XCD takes
+// runs of four consecutive tiles: a view's numerator rows rarely start on a
+// cache-line boundary, so neighbouring tiles share lines, which then come
+// from the same L2.  Blocks past the last multiple of 32 map to themselves.
+__device__ __forceinline__ int xcd_group_slot(int b, int n) {
+  const int full = n & ~31;
+  if (b >= full) return b;
+  const int x = b & 7, k = b >> 3;
+  return ((k >> 2) * 8 + x) * 4 + (k & 3);
+}
+
 template <int T, int G>
 __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ scans,
                                                     const int2* __restrict__ tmap, int F) {
@@ -983,7 +995,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   __shared__ double pden[G > 1 ? (G - 1) : 1][T * T];
   const int q = threadIdx.x >> 8;   // group
   const int t = threadIdx.x & 255;  // pixel lane within the group
-  const int2 tm = tmap[blockIdx.x];
+  const int2 tm = tmap[xcd_group_slot(blockIdx.x, gridDim.x)];
   const ScanDev& sc = scans[tm.x];
   const int tile = tm.y;
   const float2* __restrict__ opart = sc.opart;
@@ -1004,7 +1016,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   for (int k = 0; k < PPT; ++k) { num[k] = make_float2(0.f, 0.f); den[k] = 0.0; }
   const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   const size_t FF = (size_t)F * F;
-  constexpr int U = 2;
+  constexpr int U = (8 / PPT > 2) ? 8 / PPT : 2;  // views per group in flight
   int e = e0 + q;
   for (; e + (U - 1) * G < e1; e += U * G) {
     float2 vv[U][PPT];
@@ -1168,12 +1180,29 @@ __global__ __launch_bounds__(256) void k_probe_final(const ScanDev* __restrict__
   float* __restrict__ err_probe = sc.err_probe;
   const int C = sc.C;
   const int pix = blockIdx.x * 256 + threadIdx.x;
+  // chunk partials are added in chunk order; loads go out in batches of 8
   float den = 0.f;
-  for (int cc = 0; cc < C; ++cc) den += den_part[(size_t)cc * FF + pix];
+  int cc = 0;
+  for (; cc + 8 <= C; cc += 8) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = den_part[(size_t)(cc + k) * FF + pix];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) den += v[k];
+  }
+  for (; cc < C; ++cc) den += den_part[(size_t)cc * FF + pix];
   float dsum = 0.f;
   for (int m = 0; m < M; ++m) {
     float2 num = make_float2(0.f, 0.f);
-    for (int cc = 0; cc < C; ++cc) num = cadd(num, num_part[((size_t)cc * M + m) * FF + pix]);
+    int c2 = 0;
+    for (; c2 + 8 <= C; c2 += 8) {
+      float2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = num_part[((size_t)(c2 + k) * M + m) * FF + pix];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) num = cadd(num, v[k]);
+    }
+    for (; c2 < C; ++c2) num = cadd(num, num_part[((size_t)c2 * M + m) * FF + pix]);
     const float2 po = P[(size_t)m * FF + pix];
     float2 pn = po;
     if (den > 0.f) {

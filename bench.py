@@ -56,11 +56,13 @@ def measured_traffic(launch_key: str, kernel: str):
 
 # rocprofv3 name of the view kernel of each view path at frame size f
 def view_kernel_name(view_path: int, f: int) -> str:
+    # the merged paths name their kernel without the eps_psi partials, the
+    # one every iteration but the last of a call runs
     return {0: f"k_fourier_fused<{f}, 1>", 1: f"k_rows_fwd<{f}>",
-            2: f"k_fourier_stream<{f}, 1, true, false>",
-            3: f"k_fourier_stream<{f}, 1, false, false>",
-            4: f"k_fourier_stream<{f}, 1, true, true>",
-            5: f"k_fourier_stream<{f}, {2 if f >= 32 else 1}, true, true>"}[view_path]
+            2: f"k_fourier_stream<{f}, 1, true, false, true>",
+            3: f"k_fourier_stream<{f}, 1, false, false, true>",
+            4: f"k_fourier_stream<{f}, 1, true, true, false>",
+            5: f"k_fourier_stream<{f}, {2 if f >= 32 else 1}, true, true, false>"}[view_path]
 
 
 def views_alg_bytes(n, m, f):
@@ -215,6 +217,32 @@ def bench_bf16x3(scan, steps: int, warmup: int, conv_iters: int, fp32_err):
             "final_err_vs_fp32": {"bf16x3": errs[-1], "fp32": fp32_err}}
 
 
+def bench_every_psi_error(scan, steps: int, warmup: int):
+    """The headline scan with eps_psi formed in every iteration
+    (DM_FLAG_EVERY_PSI_ERROR): the view update then reads psi a second time
+    in each iteration instead of in the last one of the timed call only."""
+    import torch
+    from paper_1808_10375_amd import dm
+    dev = torch.device("cuda:0")
+    n, m = scan.n_frames, scan.n_modes
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        ctx = dm.DMContext(torch.from_numpy(scan.I).to(dev), scan.pos,
+                           torch.from_numpy(scan.P0).to(dev), torch.from_numpy(scan.O0).to(dev),
+                           beta=scan.beta, flags=dm.DM_FLAG_EVERY_PSI_ERROR, stream=stream)
+        ctx.iterate(warmup)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ctx.iterate(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        ctx.free()
+    return {"workload": "the same scan as the headline line",
+            "value": n * m / (elapsed / steps), "unit": "frame·mode/s",
+            "ms_per_step": 1e3 * elapsed / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +257,8 @@ def main():
                     help="skip the batched-scans (and other forms') measurements")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="transform form of the headline run (bf16x3: F = 128 only)")
+    ap.add_argument("--every-psi-error", action="store_true",
+                    help="form eps_psi in every iteration (DM_FLAG_EVERY_PSI_ERROR)")
     ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3, 4, 5],
                     help="override the library's default view kernel (dm_tuning.view_path)")
     ap.add_argument("--multipass", action="store_true",
@@ -273,7 +303,8 @@ def main():
         I = torch.from_numpy(scan.I).to(dev)
         P0 = torch.from_numpy(scan.P0).to(dev)
         O0 = torch.from_numpy(scan.O0).to(dev)
-        flags = dm.DM_FLAG_PHASE_TIMING | (dm.DM_FLAG_MULTIPASS if args.multipass else 0)
+        flags = (dm.DM_FLAG_PHASE_TIMING | (dm.DM_FLAG_MULTIPASS if args.multipass else 0)
+                 | (dm.DM_FLAG_EVERY_PSI_ERROR if args.every_psi_error else 0))
         prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
         ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream,
                            precision=prec)
@@ -344,7 +375,9 @@ def main():
                            "alg_flops_per_launch": flops, "avg_launch_ms": views_ms}
         out["dtype"] = "bf16x3/f32"
     if not args.no_forms and args.config == 1 and args.precision == "fp32":
-        out["forms"] = {"batched": bench_batched(args.steps, args.warmup, args.conv_iters),
+        out["forms"] = {"every_psi_error": bench_every_psi_error(scan, args.steps,
+                                                                 args.warmup),
+                        "batched": bench_batched(args.steps, args.warmup, args.conv_iters),
                         "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,
                                                errs[-1])}
     if not args.no_cpu:

@@ -203,7 +203,8 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     why = "the BF16x3 DFT form takes at most 8 modes";
     return DM_E_UNSUPPORTED;
   }
-  if (d->flags & ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH)) {
+  if (d->flags &
+      ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH | DM_FLAG_EVERY_PSI_ERROR)) {
     why = "unknown flag bits";
     return DM_E_ARG;
   }
@@ -268,8 +269,9 @@ struct dm_ctx {
   int stream_slots = 0;
   dm_tuning tune{};
   // graph of one iteration
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  // graphs of one iteration: [0] without, [1] with the eps_psi partials
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   // phase timing
   struct Mark { int phase; hipEvent_t a, b; };
   std::vector<Mark> marks;
@@ -279,8 +281,10 @@ struct dm_ctx {
   ~dm_ctx() {
     for (auto& m : marks) { event_pool.push_back(m.a); event_pool.push_back(m.b); }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int k = 0; k < 2; ++k) {
+      if (graph_exec[k]) (void)hipGraphExecDestroy(graph_exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+    }
   }
   bool timing() const { return (flags & DM_FLAG_PHASE_TIMING) != 0; }
   template <class T>
@@ -403,8 +407,10 @@ hipError_t set_cols_lds(int F, int bytes) {
 // scan descriptor table and the block maps; upload them.  Synchronises.
 dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
   c->tune = t;
-  if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
-  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  for (int k = 0; k < 2; ++k) {
+    if (c->graph_exec[k]) { (void)hipGraphExecDestroy(c->graph_exec[k]); c->graph_exec[k] = nullptr; }
+    if (c->graph[k]) { (void)hipGraphDestroy(c->graph[k]); c->graph[k] = nullptr; }
+  }
   const int n = (int)c->scans.size();
   std::vector<ScanDev> sd(n);
   std::vector<int2> tmap, cmap;
@@ -624,10 +630,21 @@ dm_status launch_views_mfma(dm_ctx* c) {
   return DM_OK;
 }
 
+template <int F, bool PE>
+void launch_merged(dm_ctx* c, int grid, int v) {
+  if (v == 2)
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, (F >= 32 ? 2 : 1), true, true, PE>), dim3(grid),
+                       dim3(F * F / (16 * (F >= 32 ? 2 : 1))), 0, c->stream, c->scan_dev(),
+                       c->vmap(), c->total_views, c->tw(), c->M, c->vscr());
+  else
+    hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, true, true, PE>), dim3(grid), dim3(F * F / 16),
+                       0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
+                       c->vscr());
+}
+
 template <int F>
-dm_status launch_views_streamed(dm_ctx* c, int vp) {
+dm_status launch_views_streamed(dm_ctx* c, int vp, bool psi_err) {
   const int grid = std::min(c->total_views, c->stream_slots);
-  constexpr int V2 = (F >= 32) ? 2 : 1;
   if (vp == DM_VIEWS_STREAMED)
     hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, true, false>), dim3(grid), dim3(F * F / 16),
                        0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
@@ -636,27 +653,27 @@ dm_status launch_views_streamed(dm_ctx* c, int vp) {
     hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, false, false>), dim3(grid), dim3(F * F / 16),
                        0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
                        c->vscr());
-  else if (vp == DM_VIEWS_STREAMED_MERGED)
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, 1, true, true>), dim3(grid), dim3(F * F / 16),
-                       0, c->stream, c->scan_dev(), c->vmap(), c->total_views, c->tw(), c->M,
-                       c->vscr());
-  else
-    hipLaunchKernelGGL((dmk::k_fourier_stream<F, V2, true, true>), dim3(grid),
-                       dim3(F * F / (16 * V2)), 0, c->stream, c->scan_dev(), c->vmap(),
-                       c->total_views, c->tw(), c->M, c->vscr());
+  else {
+    const int v = (vp == DM_VIEWS_STREAMED_WIDE) ? 2 : 1;
+    if (psi_err) launch_merged<F, true>(c, grid, v);
+    else launch_merged<F, false>(c, grid, v);
+  }
   DM_LAUNCHED(c, "k_fourier_stream");
   return DM_OK;
 }
 
-dm_status launch_views(dm_ctx* c) {
+// *psi_valid: whether the launched kernels formed the eps_psi partials
+dm_status launch_views(dm_ctx* c, bool psi_err, bool* psi_valid) {
+  *psi_valid = true;
   if (c->bf16x3()) return launch_views_mfma(c);
   const int vp = c->tune.view_path;
   if (vp >= DM_VIEWS_STREAMED) {
+    if (vp >= DM_VIEWS_STREAMED_MERGED) *psi_valid = psi_err;
     switch (c->F) {
-      case 16: return launch_views_streamed<16>(c, vp);
-      case 32: return launch_views_streamed<32>(c, vp);
-      case 64: return launch_views_streamed<64>(c, vp);
-      case 128: return launch_views_streamed<128>(c, vp);
+      case 16: return launch_views_streamed<16>(c, vp, psi_err);
+      case 32: return launch_views_streamed<32>(c, vp, psi_err);
+      case 64: return launch_views_streamed<64>(c, vp, psi_err);
+      case 128: return launch_views_streamed<128>(c, vp, psi_err);
     }
   }
   if (vp == DM_VIEWS_FUSED) {
@@ -679,12 +696,15 @@ dm_status launch_views(dm_ctx* c) {
   return DM_E_UNSUPPORTED;
 }
 
-dm_status launch_iteration(dm_ctx* c) {
+// psi_err: form the eps_psi partial sums in this iteration (the default view
+// kernel at F <= 128 skips the second read of psi they need otherwise)
+dm_status launch_iteration(dm_ctx* c, bool psi_err) {
   const int F = c->F, M = c->M, FF = F * F, nb = n_pblk(F);
   const int n = (int)c->scans.size();
   int mk;
   DM_TRY(phase_begin(c, DM_PHASE_VIEWS, &mk));
-  DM_TRY(launch_views(c));
+  bool psi_valid = true;
+  DM_TRY(launch_views(c, psi_err, &psi_valid));
   DM_TRY(phase_end(c, mk));
   DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
   if (c->tune.obj_tile == 16)
@@ -707,18 +727,20 @@ dm_status launch_iteration(dm_ctx* c) {
   DM_TRY(phase_end(c, mk));
   DM_TRY(phase_begin(c, DM_PHASE_ERRORS, &mk));
   hipLaunchKernelGGL(dmk::k_errors, dim3(n), dim3(256), 0, c->stream, c->scan_dev(), nb, M,
-                     c->flags_dev());
+                     c->flags_dev(), psi_valid ? 1 : 0);
   DM_LAUNCHED(c, "k_errors");
   DM_TRY(phase_end(c, mk));
   if (c->timing()) c->timed_iters++;
   return DM_OK;
 }
 
-// One iteration as a replayed graph (captured on first use).
-dm_status graph_iteration(dm_ctx* c) {
-  if (!c->graph_exec) {
+// One iteration as a replayed graph (captured on first use; one graph with
+// and one without the eps_psi partials).
+dm_status graph_iteration(dm_ctx* c, bool psi_err) {
+  const int k = psi_err ? 1 : 0;
+  if (!c->graph_exec[k]) {
     DM_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    dm_status s = launch_iteration(c);
+    dm_status s = launch_iteration(c, psi_err);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (s != DM_OK) {
@@ -726,10 +748,10 @@ dm_status graph_iteration(dm_ctx* c) {
       return s;
     }
     if (e != hipSuccess) return fail_hip(c, e, "hipStreamEndCapture");
-    c->graph = g;
-    DM_HIP(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    c->graph[k] = g;
+    DM_HIP(c, hipGraphInstantiate(&c->graph_exec[k], c->graph[k], nullptr, nullptr, 0));
   }
-  DM_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+  DM_HIP(c, hipGraphLaunch(c->graph_exec[k], c->stream));
   return DM_OK;
 }
 
@@ -996,7 +1018,7 @@ dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
   DM_TRY(apply_tuning(c, t));
   const uint32_t saved_flags = c->flags;
   c->flags &= ~DM_FLAG_PHASE_TIMING;
-  dm_status s = launch_iteration(c);  // warm-up
+  dm_status s = launch_iteration(c, false);  // warm-up
   std::vector<double> v;
   for (int r = 0; r < reps && s == DM_OK; ++r) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -1004,7 +1026,7 @@ dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
     if (e == hipSuccess) e = take_event(c, &b);
     if (e == hipSuccess) e = hipEventRecord(a, c->stream);
     if (e != hipSuccess) { s = fail_hip(c, e, "autotune events"); break; }
-    s = launch_iteration(c);
+    s = launch_iteration(c, false);
     if (s != DM_OK) break;
     e = hipEventRecord(b, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -1060,7 +1082,8 @@ dm_status dm_iterate(dm_ctx* c, int32_t n_iter) {
   if (s != DM_OK) return s;
   if (n_iter < 0) { c->err = "n_iter < 0"; return DM_E_ARG; }
   for (int i = 0; i < n_iter; ++i) {
-    s = (c->flags & DM_FLAG_GRAPH) ? graph_iteration(c) : launch_iteration(c);
+    const bool psi_err = (i == n_iter - 1) || (c->flags & DM_FLAG_EVERY_PSI_ERROR);
+    s = (c->flags & DM_FLAG_GRAPH) ? graph_iteration(c, psi_err) : launch_iteration(c, psi_err);
     if (s != DM_OK) return s;
     c->iters++;
   }

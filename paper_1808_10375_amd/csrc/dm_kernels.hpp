@@ -504,15 +504,21 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
 //           goes back to scratch and
 //   pass 3  per mode: Z' from scratch, the view update and the numerator
 //           (no transform runs while the numerator is live)
-// Every mode is transformed twice (no recomputation); psi is read twice and
-// written once, with the non-temporal hint (NT) so the probe and the object
-// stay in L2.  A thread runs V virtual threads of the transform (F*F/(16 V)
+// Every mode is transformed twice (no recomputation); psi is written once
+// and read once or twice, with the non-temporal hint (NT) so the probe and
+// the object stay in L2.  The merged form without PSI_ERR never reads psi
+// in pass 2: since psi = 2 P O - Z and the transforms are linear,
+//   psi' = psi + beta (Z' - P O) = (2 - beta) P O + F^-1[(beta g - 1/F^2) Z~]
+// (the unnormalised inverse of the spectrum scaled by beta g - 1/F^2 is
+// beta Z' - Z), so one inverse transform gives psi' directly.  What it
+// cannot give is psi' - psi, so the eps_psi partial sums are left at zero;
+// with PSI_ERR the update reads psi again and forms them.  A thread runs V virtual threads of the transform (F*F/(16 V)
 // threads).  With V = 1 (128 registers a thread) the merged form parks the
 // scale to make room for the numerator: the rows that fit beside the
 // exchange buffer in LDS, the rest in the slot; with V = 2 (256 registers)
 // the scale and the numerator both stay in registers.
 // ---------------------------------------------------------------------------
-template <int F, int V, bool NT_HINT, bool MERGE>
+template <int F, int V, bool NT_HINT, bool MERGE, bool PSI_ERR = true>
 __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
     const float2* __restrict__ tw, int M, float2* __restrict__ vscr) {
@@ -522,6 +528,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
   constexpr int LD = F + 1;
   constexpr int FF = F * F;
   constexpr bool kPark = MERGE && V == 1;
+  constexpr bool kDirect = MERGE && !PSI_ERR;  // psi' without reading psi
   constexpr bool kKeep = kPark;  // keeps the last spectrum in registers
   // scale rows parked in LDS: as many as fit in 160 KB beside the rest
   constexpr int kLdsFixed = F * LD * 8 + 2 * ((NT + 63) / 64) * 4 + F * 8 + 256;
@@ -621,7 +628,8 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
             const int l = (g + B * i) + 16 * l2;
             const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
             const float sv = S[v][r];
-            S[v][r] = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+            const float g = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+            S[v][r] = kDirect ? beta * g - inv_ff : g;
           }
       }
       __syncthreads();  // bI aliases the exchange buffer
@@ -664,6 +672,32 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
           }
         }
     };
+    // psi' = (2 - beta) P O + W of mode m from W = beta Z' - Z (wp(v, u))
+    auto update_direct = [&](int m, auto wp_of) {
+      const int sm = m * FF * 8;
+      const float c2 = 2.f - beta;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int b = 0; b < 16; b += KB) {
+          float2 pr[KB], ov[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            pr[k] = bload2(rP, vF, sm + rowF(v, b + k));
+            ov[k] = bload2(rO, vO, sO + rowO(v, b + k));
+          }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            const float2 phi = cmul(pr[k], ov[k]);
+            const float2 w = wp_of(v, b + k);
+            const float2 pn = make_float2(c2 * phi.x + w.x, c2 * phi.y + w.y);
+            if (NT_HINT) bstore2_nt(rpsi, pn, vF, sm + rowF(v, b + k));
+            else bstore2(rpsi, pn, vF, sm + rowF(v, b + k));
+            e_n += cabs2(pn);
+            oacc[v][b + k] = cadd(oacc[v][b + k], cmulc(pr[k], pn));
+          }
+        }
+    };
     // ---- pass 2: scaled spectra back to the spatial domain
     if constexpr (kPark) {
 #pragma unroll
@@ -693,7 +727,9 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
           for (int r = 0; r < 16; ++r) a[v][r] = cscale(a[v][r], S[v][r]);
       }
       Frame2D<F, 1, V>::inv(a, buf, twl, c, g0);
-      if constexpr (MERGE) {
+      if constexpr (kDirect) {
+        update_direct(m, [&](int v, int u) { return a[v][u]; });
+      } else if constexpr (MERGE) {
         update(m, [&](int v, int u) { return a[v][u]; });
       } else {
 #pragma unroll
@@ -1238,8 +1274,10 @@ __device__ double block_sum_d(double x, double* red) {
   return r;
 }
 
+// psi_valid = 0: this iteration's view kernel formed no eps_psi partials;
+// eps_psi is then reported as NaN and not taken for divergence.
 __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scans, int n_pblk,
-                                                int M, int* __restrict__ flags) {
+                                                int M, int* __restrict__ flags, int psi_valid) {
   __shared__ double red[256];
   const ScanDev& sc = scans[blockIdx.x];
   const float* __restrict__ err_psi = sc.err_psi;
@@ -1275,10 +1313,12 @@ __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scan
     const int it = *counter;
     DevErrors e;
     e.iter = it + 1;
-    e.eps_psi = (v[1] > 0) ? (float)sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.f);
+    e.eps_psi = !psi_valid ? NAN
+                : (v[1] > 0) ? (float)sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.f);
     e.eps_obj = (v[3] > 0) ? (float)sqrt(v[2] / v[3]) : (v[2] > 0 ? INFINITY : 0.f);
     e.eps_probe = (pn_tot > 0) ? (float)sqrt(pd_tot / pn_tot) : (pd_tot > 0 ? INFINITY : 0.f);
-    bool bad = !isfinite(e.eps_psi) || !isfinite(e.eps_obj) || !isfinite(e.eps_probe);
+    bool bad = (psi_valid && !isfinite(e.eps_psi)) || !isfinite(e.eps_obj) ||
+               !isfinite(e.eps_probe);
     for (int m = 0; m < 16; ++m) {
       e.eps_mode[m] = (m < M) ? modes[m] : 0.f;
       if (m < M && !isfinite(modes[m])) bad = true;

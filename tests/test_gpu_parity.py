@@ -274,3 +274,57 @@ def test_flyscan_256_strip_one_step():
     say("case fly-scan strip of 24 views, F=256, M=8")
     psi0 = oracle.init_views(s.P0, s.O0, s.pos).astype(np.complex64)
     one_step_case(dict(psi=psi0, P=s.P0, O=s.O0, I=s.I, pos=s.pos, beta=0.8))
+
+
+@pytest.mark.parametrize("view_path", [4, 5])
+@pytest.mark.parametrize("seed,n,f,m,h,w", [(41, 29, 32, 2, 96, 90), (42, 21, 64, 3, 180, 150),
+                                            (43, 13, 128, 5, 260, 250)])
+def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
+    """The merged streamed kernels compute psi' = (2 - beta) P O +
+    F^-1[(beta g - 1/F^2) Z~] in every iteration but the last of a call
+    (Eq. 3 rewritten; no second read of psi).  Three iterations in one call
+    against three oracle iterations, and against the same call with
+    DM_FLAG_EVERY_PSI_ERROR (the direct form in every iteration): states to
+    the one-step bar, eps_psi NaN in the first two iterations only, and
+    equal to the oracle's in the last."""
+    from paper_1808_10375_amd import dm
+    torch = _torch()
+    say(f"case psi-free update view_path={view_path} seed={seed} N={n} F={f} M={m}")
+    c = synth.random_case(seed, n, f, m, h, w, perturb=0.3)
+    psi, P, O = (c["psi"].astype(np.complex128), c["P"].astype(np.complex128),
+                 c["O"].astype(np.complex128))
+    hist_o = []
+    for _ in range(3):
+        psi, P, O, e_o = oracle.iterate(psi, P, O, c["pos"], c["I"].astype(np.float64), c["beta"])
+        hist_o.append(e_o)
+    den_o = oracle.object_update(psi, P, O, c["pos"])[1]
+    dev = torch.device("cuda:0")
+    res = {}
+    for flags in (0, dm.DM_FLAG_EVERY_PSI_ERROR):
+        It = torch.from_numpy(np.ascontiguousarray(c["I"], dtype=np.float32)).to(dev)
+        Pt = torch.from_numpy(np.ascontiguousarray(c["P"], dtype=np.complex64)).to(dev)
+        Ot = torch.from_numpy(np.ascontiguousarray(c["O"], dtype=np.complex64)).to(dev)
+        ctx = dm.DMContext(It, c["pos"], Pt, Ot, beta=c["beta"], flags=flags)
+        t = ctx.tuning()
+        ctx.set_tuning(t["obj_tile"], t["probe_chunks"], view_path)
+        ctx.set_state(torch.from_numpy(np.ascontiguousarray(c["psi"])).to(dev), Pt, Ot, 0)
+        ctx.iterate(3)
+        hist = ctx.error_history()
+        psi_g, P_g, O_g, it = ctx.state()
+        res[flags] = (psi_g.cpu().numpy(), P_g.cpu().numpy(), O_g.cpu().numpy(), hist)
+        ctx.free()
+        assert it == 3
+    for flags, (psi_g, P_g, O_g, hist) in res.items():
+        r = (rel(psi_g, psi), rel_weighted(O_g, O, den_o), rel(P_g, P))
+        say(f"  flags={flags}: rel L2 psi {r[0]:.2e} O(weighted) {r[1]:.2e} P {r[2]:.2e}")
+        assert max(r) <= 2 * TOL, r
+        check_errors(hist[-1], hist_o[-1])
+        for k in range(2):
+            e = hist[k]
+            assert np.isfinite(e["eps_probe"]) and np.isfinite(e["eps_obj"])
+            if flags == 0:
+                assert np.isnan(e["eps_psi"])
+            else:
+                assert abs(e["eps_psi"] - hist_o[k]["eps_psi"]) <= 1e-4 * hist_o[k]["eps_psi"]
+    a, b = res[0], res[dm.DM_FLAG_EVERY_PSI_ERROR]
+    assert rel(a[0], b[0]) <= TOL and rel(a[1], b[1]) <= TOL

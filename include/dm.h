@@ -99,17 +99,16 @@ typedef enum {
                                     iteration; needs a non-NULL stream and
                                     excludes DM_FLAG_PHASE_TIMING           */
 
-#define DM_FLAG_EVERY_PSI_ERROR 8u /* form eps_psi in every iteration.  By
-                                    default it is formed in the last
-                                    iteration of each dm_iterate call only:
-                                    it needs psi' - psi, and the default view
-                                    kernel at F <= 128 (the merged streamed
-                                    paths) otherwise computes psi' without
-                                    reading psi a second time (psi' =
-                                    (2 - beta) P O + F^-1[(beta g - 1/F^2)
-                                    F(2 P O - psi)], g the F_c scale, which
-                                    is Eq. 3 rewritten).  The other iterations
-                                    of a call report eps_psi as NaN.        */
+#define DM_FLAG_PSI_ERROR_LAST 8u /* form eps_psi only in the last iteration
+                                    of each dm_iterate call (by default:
+                                    every iteration).  The other iterations
+                                    then run the merged streamed view kernels
+                                    (F <= 128) without a second read of psi:
+                                    psi' = (2 - beta) P O + F^-1[(beta g -
+                                    1/F^2) F(2 P O - psi)], g the F_c scale,
+                                    which is Eq. 3 rewritten; psi' - psi is
+                                    not formed there and eps_psi is reported
+                                    as NaN.                                 */
 
 /* Phases of one iteration, in launch order (indices of dm_phase_times). */
 #define DM_PHASE_VIEWS 0         /* Eq. 3 with F_c: exit waves, transforms,
@@ -176,7 +175,7 @@ typedef struct {
 typedef struct {
   int32_t iter;        /* 1-based index of the iteration these belong to  */
   float eps_psi;       /* ||psi' - psi|| / ||psi'||; NaN where not formed
-                          (see DM_FLAG_EVERY_PSI_ERROR)                   */
+                          (see DM_FLAG_PSI_ERROR_LAST)                    */
   float eps_obj;       /* ||O' - O|| / ||O'|| over covered object pixels  */
   float eps_probe;     /* Eq. 6 with the mode sum inside both norms; the
                           convergence error "err"                        */

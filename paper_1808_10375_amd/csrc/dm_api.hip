@@ -204,7 +204,7 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     return DM_E_UNSUPPORTED;
   }
   if (d->flags &
-      ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH | DM_FLAG_EVERY_PSI_ERROR)) {
+      ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH | DM_FLAG_PSI_ERROR_LAST)) {
     why = "unknown flag bits";
     return DM_E_ARG;
   }
@@ -696,8 +696,8 @@ dm_status launch_views(dm_ctx* c, bool psi_err, bool* psi_valid) {
   return DM_E_UNSUPPORTED;
 }
 
-// psi_err: form the eps_psi partial sums in this iteration (the default view
-// kernel at F <= 128 skips the second read of psi they need otherwise)
+// psi_err: form the eps_psi partial sums in this iteration (without them the
+// merged view kernels at F <= 128 skip the second read of psi)
 dm_status launch_iteration(dm_ctx* c, bool psi_err) {
   const int F = c->F, M = c->M, FF = F * F, nb = n_pblk(F);
   const int n = (int)c->scans.size();
@@ -1082,7 +1082,7 @@ dm_status dm_iterate(dm_ctx* c, int32_t n_iter) {
   if (s != DM_OK) return s;
   if (n_iter < 0) { c->err = "n_iter < 0"; return DM_E_ARG; }
   for (int i = 0; i < n_iter; ++i) {
-    const bool psi_err = (i == n_iter - 1) || (c->flags & DM_FLAG_EVERY_PSI_ERROR);
+    const bool psi_err = (i == n_iter - 1) || !(c->flags & DM_FLAG_PSI_ERROR_LAST);
     s = (c->flags & DM_FLAG_GRAPH) ? graph_iteration(c, psi_err) : launch_iteration(c, psi_err);
     if (s != DM_OK) return s;
     c->iters++;

@@ -30,7 +30,7 @@ DM_BF16X3_DFT = 1
 DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 256)
 DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
 DM_FLAG_GRAPH = 4         # capture one iteration into a hipGraph and replay it
-DM_FLAG_EVERY_PSI_ERROR = 8  # form eps_psi in every iteration (default: last of each call)
+DM_FLAG_PSI_ERROR_LAST = 8  # eps_psi in the last iteration of a call only (psi-free update)
 DM_VIEWS_FUSED = 0            # dm_tuning.view_path values
 DM_VIEWS_THREE_KERNEL = 1
 DM_VIEWS_STREAMED = 2

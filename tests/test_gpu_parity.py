@@ -280,13 +280,13 @@ def test_flyscan_256_strip_one_step():
 @pytest.mark.parametrize("seed,n,f,m,h,w", [(41, 29, 32, 2, 96, 90), (42, 21, 64, 3, 180, 150),
                                             (43, 13, 128, 5, 260, 250)])
 def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
-    """The merged streamed kernels compute psi' = (2 - beta) P O +
-    F^-1[(beta g - 1/F^2) Z~] in every iteration but the last of a call
-    (Eq. 3 rewritten; no second read of psi).  Three iterations in one call
-    against three oracle iterations, and against the same call with
-    DM_FLAG_EVERY_PSI_ERROR (the direct form in every iteration): states to
-    the one-step bar, eps_psi NaN in the first two iterations only, and
-    equal to the oracle's in the last."""
+    """With DM_FLAG_PSI_ERROR_LAST the merged streamed kernels compute
+    psi' = (2 - beta) P O + F^-1[(beta g - 1/F^2) Z~] in every iteration but
+    the last of a call (Eq. 3 rewritten; no second read of psi).  Three
+    iterations in one call against three oracle iterations, and against the
+    same call without the flag (the direct form in every iteration): states
+    to the one-step bar, eps_psi NaN in the first two iterations with the
+    flag only, and equal to the oracle's wherever it is formed."""
     from paper_1808_10375_amd import dm
     torch = _torch()
     say(f"case psi-free update view_path={view_path} seed={seed} N={n} F={f} M={m}")
@@ -300,7 +300,7 @@ def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
     den_o = oracle.object_update(psi, P, O, c["pos"])[1]
     dev = torch.device("cuda:0")
     res = {}
-    for flags in (0, dm.DM_FLAG_EVERY_PSI_ERROR):
+    for flags in (0, dm.DM_FLAG_PSI_ERROR_LAST):
         It = torch.from_numpy(np.ascontiguousarray(c["I"], dtype=np.float32)).to(dev)
         Pt = torch.from_numpy(np.ascontiguousarray(c["P"], dtype=np.complex64)).to(dev)
         Ot = torch.from_numpy(np.ascontiguousarray(c["O"], dtype=np.complex64)).to(dev)
@@ -322,9 +322,9 @@ def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
         for k in range(2):
             e = hist[k]
             assert np.isfinite(e["eps_probe"]) and np.isfinite(e["eps_obj"])
-            if flags == 0:
+            if flags == dm.DM_FLAG_PSI_ERROR_LAST:
                 assert np.isnan(e["eps_psi"])
             else:
                 assert abs(e["eps_psi"] - hist_o[k]["eps_psi"]) <= 1e-4 * hist_o[k]["eps_psi"]
-    a, b = res[0], res[dm.DM_FLAG_EVERY_PSI_ERROR]
+    a, b = res[0], res[dm.DM_FLAG_PSI_ERROR_LAST]
     assert rel(a[0], b[0]) <= TOL and rel(a[1], b[1]) <= TOL

@@ -532,18 +532,17 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
   constexpr bool kDirect = MERGE && !PSI_ERR;  // psi' without reading psi
   constexpr bool kKeep = kPark;  // keeps the last spectrum in registers
   // scale rows parked in LDS: as many as fit in 160 KB beside the rest
-  constexpr int kLdsFixed = F * LD * 8 + 2 * ((NT + 63) / 64) * 4 + F * 8 + 256;
+  constexpr int kLdsFixed = F * LD * 8 + 2 * ((NT + 63) / 64) * 4 + 256;
   constexpr int kLdsRows = !kPark ? 0
                            : ((163840 - kLdsFixed) / (NT * 4) < 16 ? (163840 - kLdsFixed) / (NT * 4)
                                                                    : 16);
   __shared__ float2 buf[F * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
-  __shared__ float2 twl[F];
   __shared__ float gl[kLdsRows > 0 ? kLdsRows * NT : 1];
 
+  // twiddles come straight from the global table: their index is
+  // wave-uniform for F >= 64, so they are scalar loads
   const int t = threadIdx.x;
-  for (int i = t; i < F; i += NT) twl[i] = tw[i];
-  __syncthreads();
   const int c = t % F;
   const int g0 = wave_uniform_div<F>(t);
   // slot: the spectra [M][V][16][NT] complex, then the modulus scale [16][NT]
@@ -613,7 +612,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
             a[v][b + k] = make_float2(2.f * phi.x - ps[k].x, 2.f * phi.y - ps[k].y);
           }
         }
-      Frame2D<F, -1, V>::fwd(a, buf, twl, c, g0);
+      Frame2D<F, -1, V>::fwd(a, buf, tw, c, g0);
       // merged form: the last mode's spectrum stays in registers for pass 2
       const bool keep = kKeep && (m == M - 1);
 #pragma unroll
@@ -741,7 +740,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
 #pragma unroll
           for (int r = 0; r < 16; ++r) a[v][r] = cscale(a[v][r], S[v][r]);
       }
-      Frame2D<F, 1, V>::inv(a, buf, twl, c, g0);
+      Frame2D<F, 1, V>::inv(a, buf, tw, c, g0);
       if constexpr (kDirect) {
         update_direct(m, [&](int v, int u) { return a[v][u]; });
       } else if constexpr (MERGE) {

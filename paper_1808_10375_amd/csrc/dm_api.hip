@@ -539,7 +539,7 @@ dm_status launch_views_multipass(dm_ctx* c) {
   DM_LAUNCHED(c, "k_rows_fwd");
   const int cb = cols_per_block(F, M);
   const size_t lds = (size_t)cb * M * (F + 1) * sizeof(float2);
-  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views, F / cb), dim3(cb * B * M), lds,
+  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views * (F / cb)), dim3(cb * B * M), lds,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M, cb);
   DM_LAUNCHED(c, "k_cols");
   hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,

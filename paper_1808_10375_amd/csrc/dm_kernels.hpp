@@ -306,6 +306,17 @@ __device__ __forceinline__ int xcd_slot(int b, int nblocks) {
   return (x < full) ? x * per + k : full * per + (x - full) * (per - 1) + k;
 }
 
+// Workgroup b runs on XCD b mod 8.  Map the blocks so that each XCD takes
+// runs of four consecutive tiles: a view's numerator rows rarely start on a
+// cache-line boundary, so neighbouring tiles share lines, which then come
+// from the same L2.  Blocks past the last multiple of 32 map to themselves.
+__device__ __forceinline__ int xcd_group_slot(int b, int n) {
+  const int full = n & ~31;
+  if (b >= full) return b;
+  const int x = b & 7, k = b >> 3;
+  return ((k >> 2) * 8 + x) * 4 + (k & 3);
+}
+
 template <int F, int V>
 __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap, int total,
@@ -842,6 +853,9 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 // (2) DFT along columns for CB columns of every mode of one view, the mode
 // sum, the modulus scale, and the inverse DFT along columns, in place in T.
 // Block = CB * B * M threads; dynamic LDS = CB * M * (F + 1) float2.
+// One-dimensional grid of views x (F / CB) column blocks, mapped so that
+// each XCD takes runs of four neighbouring column blocks of one view: a
+// block's rows are CB * 8 bytes wide, so neighbours share cache lines.
 template <int F>
 __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans,
                                                const int2* __restrict__ vmap,
@@ -849,12 +863,14 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
   constexpr int B = F / 16, LD = F + 1, FF = F * F, NI = 16 / B;
   extern __shared__ float2 dyn[];
   const int t = threadIdx.x;
-  const int2 vm = vmap[blockIdx.x];
+  const int nblk = F / CB;
+  const int slot = xcd_group_slot(blockIdx.x, gridDim.x);
+  const int2 vm = vmap[slot / nblk];
   const ScanDev& sc = scans[vm.x];
   const int j = uni(vm.y);
   float2* __restrict__ T = sc.tspec;
   const float* __restrict__ I = sc.I;
-  const int col0 = blockIdx.y * CB;
+  const int col0 = (slot % nblk) * CB;
   const int c = t % CB;
   const int rest = t / CB;
   const int n2 = rest % B;
@@ -1024,17 +1040,6 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 // sums of each pixel are then added in group order through LDS.  The order of
 // every sum is fixed, so results are bitwise reproducible.
 // ---------------------------------------------------------------------------
-// Workgroup b runs on XCD b mod 8.  Map the blocks so that each XCD takes
-// runs of four consecutive tiles: a view's numerator rows rarely start on a
-// cache-line boundary, so neighbouring tiles share lines, which then come
-// from the same L2.  Blocks past the last multiple of 32 map to themselves.
-__device__ __forceinline__ int xcd_group_slot(int b, int n) {
-  const int full = n & ~31;
-  if (b >= full) return b;
-  const int x = b & 7, k = b >> 3;
-  return ((k >> 2) * 8 + x) * 4 + (k & 3);
-}
-
 template <int T, int G>
 __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ scans,
                                                     const int2* __restrict__ tmap, int F) {

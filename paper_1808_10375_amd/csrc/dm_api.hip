@@ -59,11 +59,20 @@ dm_tuning default_tuning(const dm_desc& d) {
   return t;
 }
 
+// dynamic LDS of k_cols: the exchange buffer (cb * M lines of
+// 16 (F / 16 + 1) + 2 complex) or, aliasing it, the mode-sum and scale rows
+// ((M + 1) * cb rows of F + 4 floats), whichever is larger
+size_t cols_lds_bytes(int F, int M, int cb) {
+  const size_t line = 16 * (F / 16 + 1) + 2;
+  return std::max((size_t)cb * M * line * sizeof(float2),
+                  (size_t)(M + 1) * cb * (F + 4) * sizeof(float));
+}
+
 int cols_per_block(int F, int M) {
   const int B = F / 16;
   int cb = 1024 / (B * M);
   int p = 1;
-  while (p * 2 <= cb && p * 2 <= 16) p *= 2;
+  while (p * 2 <= cb && p * 2 <= 16 && cols_lds_bytes(F, M, p * 2) <= 160 * 1024) p *= 2;
   return p;
 }
 
@@ -478,7 +487,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
                            hipMemcpyHostToDevice, c->stream));
   if (t.view_path == DM_VIEWS_THREE_KERNEL) {
     const int lds =
-        (int)((size_t)cols_per_block(c->F, c->M) * c->M * (c->F + 1) * sizeof(float2));
+        (int)cols_lds_bytes(c->F, c->M, cols_per_block(c->F, c->M));
     DM_HIP(c, set_cols_lds(c->F, lds));
   }
   DM_HIP(c, hipStreamSynchronize(c->stream));
@@ -538,7 +547,7 @@ dm_status launch_views_multipass(dm_ctx* c) {
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_rows_fwd");
   const int cb = cols_per_block(F, M);
-  const size_t lds = (size_t)cb * M * (F + 1) * sizeof(float2);
+  const size_t lds = cols_lds_bytes(F, M, cb);
   hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views * (F / cb)), dim3(cb * B * M), lds,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M, cb);
   DM_LAUNCHED(c, "k_cols");

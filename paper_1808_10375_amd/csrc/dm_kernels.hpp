@@ -797,12 +797,27 @@ struct RowCfg {
   static constexpr int NT = RB * B;
 };
 
+// LDS layout of the 16 x B exchange of one line (row or column) in the
+// multi-pass kernels: element (k1, n2) at k1 * (B + 1) + n2.  Writes by k1
+// (lanes along n2) are consecutive; reads by n2 (lanes along k1) step B + 1
+// complex values, which spreads them over the banks.  Lines are XL_ROW (row
+// kernels: rows of a 16-lane group land on disjoint banks) or XL_COL (column
+// kernel, whose lanes run over 8 columns first) complex values apart.
+template <int F>
+struct XCfg {
+  static constexpr int B = F / 16;
+  static constexpr int XS = B + 1;
+  static constexpr int XL_ROW = 16 * (B + 1) + 8;
+  static constexpr int XL_COL = 16 * (B + 1) + 2;
+};
+
 // (1) Z = 2 P O - psi and the DFT along rows, RB rows per block.
 template <int F>
 __global__ __launch_bounds__(256) void k_rows_fwd(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
     const float2* __restrict__ tw, int M) {
-  constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
+  constexpr int B = F / 16, RB = RowCfg<F>::RB, FF = F * F, NI = 16 / B;
+  constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_ROW;
   __shared__ float2 buf[RB * LD];
   const int t = threadIdx.x;
   const int2 vm = vmap[blockIdx.x / M];
@@ -834,12 +849,12 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 #pragma unroll
     for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, n2 * k1, a[k1]);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) buf[rl * LD + k1 * B + n2] = a[k1];
+    for (int k1 = 0; k1 < 16; ++k1) buf[rl * LD + k1 * XS + n2] = a[k1];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int q = 0; q < B; ++q) a[i * B + q] = buf[rl * LD + (n2 + B * i) * B + q];
+      for (int q = 0; q < B; ++q) a[i * B + q] = buf[rl * LD + (n2 + B * i) * XS + q];
 #pragma unroll
     for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
   }
@@ -852,7 +867,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 
 // (2) DFT along columns for CB columns of every mode of one view, the mode
 // sum, the modulus scale, and the inverse DFT along columns, in place in T.
-// Block = CB * B * M threads; dynamic LDS = CB * M * (F + 1) float2.
+// Block = CB * B * M threads; dynamic LDS: CB * M lines of XL_COL complex.
 // One-dimensional grid of views x (F / CB) column blocks, mapped so that
 // each XCD takes runs of four neighbouring column blocks of one view: a
 // block's rows are CB * 8 bytes wide, so neighbours share cache lines.
@@ -860,7 +875,8 @@ template <int F>
 __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans,
                                                const int2* __restrict__ vmap,
                                                const float2* __restrict__ tw, int M, int CB) {
-  constexpr int B = F / 16, LD = F + 1, FF = F * F, NI = 16 / B;
+  constexpr int B = F / 16, FF = F * F, NI = 16 / B;
+  constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_COL;
   extern __shared__ float2 dyn[];
   const int t = threadIdx.x;
   const int nblk = F / CB;
@@ -885,36 +901,46 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
 #pragma unroll
     for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<-1>(tw, n2 * k1, a[k1]);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) dyn[line * LD + k1 * B + n2] = a[k1];
+    for (int k1 = 0; k1 < 16; ++k1) dyn[line * LD + k1 * XS + n2] = a[k1];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int q = 0; q < B; ++q) a[i * B + q] = dyn[line * LD + (n2 + B * i) * B + q];
+      for (int q = 0; q < B; ++q) a[i * B + q] = dyn[line * LD + (n2 + B * i) * XS + q];
 #pragma unroll
     for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
   }
-  // mode sum through LDS (aliases the exchange buffer)
+  // mode sum and scale through LDS (aliasing the exchange buffer): |Z~|^2
+  // of every mode -> s; each thread then forms the scale of CB * F / NT
+  // pixels from the M partial values and I (column-major pixel order, so a
+  // wave reads consecutive LDS words and consecutive rows of I), writes it to
+  // g, and reads back the scale of its own 16 pixels.  Rows of s and g are
+  // padded to F + 4 words: the 8 columns x 4 row offsets a half-wave touches
+  // fall in distinct banks.
+  constexpr int LS = F + 4;
   float* s = reinterpret_cast<float*>(dyn);
+  float* gsh = s + (size_t)M * CB * LS;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) s[line * F + (n2 + B * i) + 16 * k2] = cabs2(a[i * B + k2]);
+    for (int k2 = 0; k2 < B; ++k2) s[line * LS + (n2 + B * i) + 16 * k2] = cabs2(a[i * B + k2]);
   __syncthreads();
-  const float* __restrict__ Ij = I + (size_t)j * FF + col0 + c;
+  const float* __restrict__ Ij = I + (size_t)j * FF + col0;
   const float inv_ff = 1.0f / (float)FF;
+  for (int p = t; p < CB * F; p += blockDim.x) {
+    const int cc = p / F, kk = p - cc * F;
+    float sum = 0.f;
+    for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + cc) * LS + kk];
+    const float iv = fmaxf(Ij[(size_t)kk * F + cc], 0.f);
+    gsh[cc * LS + kk] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+  }
+  __syncthreads();
   float gs[16];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) {
-      const int kk = (n2 + B * i) + 16 * k2;
-      float sum = 0.f;
-      for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + c) * F + kk];
-      const float iv = fmaxf(Ij[(size_t)kk * F], 0.f);
-      gs[i * B + k2] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
-    }
+    for (int k2 = 0; k2 < B; ++k2) gs[i * B + k2] = gsh[c * LS + (n2 + B * i) + 16 * k2];
 #pragma unroll
   for (int r = 0; r < 16; ++r) a[r] = cscale(a[r], gs[r]);
   __syncthreads();
@@ -924,10 +950,10 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int q = 0; q < B; ++q) dyn[line * LD + (n2 + B * i) * B + q] = a[i * B + q];
+      for (int q = 0; q < B; ++q) dyn[line * LD + (n2 + B * i) * XS + q] = a[i * B + q];
     __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) a[k1] = dyn[line * LD + k1 * B + n2];
+    for (int k1 = 0; k1 < 16; ++k1) a[k1] = dyn[line * LD + k1 * XS + n2];
 #pragma unroll
     for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, n2 * k1, a[k1]);
   }
@@ -942,7 +968,8 @@ template <int F>
 __global__ __launch_bounds__(256) void k_rows_inv(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
     const float2* __restrict__ tw, int M) {
-  constexpr int B = F / 16, RB = RowCfg<F>::RB, LD = F + 1, FF = F * F, NI = 16 / B;
+  constexpr int B = F / 16, RB = RowCfg<F>::RB, FF = F * F, NI = 16 / B;
+  constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_ROW;
   constexpr int NT = RowCfg<F>::NT;
   __shared__ float2 buf[RB * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
@@ -982,10 +1009,10 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 #pragma unroll
       for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int q = 0; q < B; ++q) buf[rl * LD + (n2 + B * i) * B + q] = a[i * B + q];
+        for (int q = 0; q < B; ++q) buf[rl * LD + (n2 + B * i) * XS + q] = a[i * B + q];
       __syncthreads();
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) a[k1] = buf[rl * LD + k1 * B + n2];
+      for (int k1 = 0; k1 < 16; ++k1) a[k1] = buf[rl * LD + k1 * XS + n2];
 #pragma unroll
       for (int k1 = 1; k1 < 16; ++k1) a[k1] = twiddle<1>(tw, n2 * k1, a[k1]);
     }

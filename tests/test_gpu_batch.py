@@ -126,6 +126,51 @@ def test_graph_replays_equal_eager_launches():
     e.free()
 
 
+def test_graphs_with_psi_error_last_equal_eager_launches():
+    """DM_FLAG_PSI_ERROR_LAST with graph replay: each context keeps one graph
+    without and one with the eps_psi partials (the last iteration of a
+    call).  Calls of 3 and 2 iterations replayed against the same calls
+    launched eagerly: bitwise equal states and errors, eps_psi NaN in every
+    iteration but the last of each call; and within 1e-5 of the direct
+    update in every iteration (no flag)."""
+    torch = _torch()
+    from paper_1808_10375_amd import dm
+    scans = uneven_scans(seed=70, sizes=(9, 14), f=128, m=2, objs=(200, 180))
+    say("case graphs with DM_FLAG_PSI_ERROR_LAST vs eager, calls of 3 and 2 iterations")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = dm.DMBatch(scans, flags=dm.DM_FLAG_GRAPH | dm.DM_FLAG_PSI_ERROR_LAST,
+                       stream=stream)
+    e = dm.DMBatch(scans, flags=dm.DM_FLAG_PSI_ERROR_LAST)
+    d = dm.DMBatch(scans)
+    done = 0
+    for n in (3, 2):
+        g.iterate(n)
+        e.iterate(n)
+        d.iterate(n)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        done += n
+        for s in range(len(scans)):
+            og, oe, pg, pe, pd = g.object(s), e.object(s), g.probe(s), e.probe(s), d.probe(s)
+            stream.synchronize()
+            torch.cuda.synchronize()
+            assert torch.equal(og, oe), (done, s)
+            assert torch.equal(pg, pe), (done, s)
+            assert rel(pg.cpu().numpy(), pd.cpu().numpy()) <= 1e-5
+            hg = g.error_history(s, 1, done)
+            he = e.error_history(s, 1, done)
+            for k, (x, y) in enumerate(zip(hg, he)):
+                last = (k + 1 == 3) or (k + 1 == done)
+                assert np.isnan(x["eps_psi"]) != last, (done, s, k)
+                assert x["eps_probe"] == y["eps_probe"] and x["eps_obj"] == y["eps_obj"]
+                if last:
+                    assert x["eps_psi"] == y["eps_psi"]
+    g.free()
+    e.free()
+    d.free()
+
+
 @pytest.mark.parametrize("tile,chunks,view_path", [(32, 16, 0), (16, 3, 0), (32, 64, 1),
                                                    (16, 16, 2), (32, 8, 3), (16, 8, 4),
                                                    (32, 16, 5)])

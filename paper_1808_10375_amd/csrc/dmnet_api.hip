@@ -23,7 +23,8 @@ struct Conv {
 };
 
 // pixels per block of the matrix-core weight gradient (a multiple of 32)
-constexpr int kWgradChunk = 4096;
+constexpr int kWgradChunk = 1024;
+constexpr int kVGradChunk = 1024;  // positions per partial of the vector-unit gradients
 
 struct Shape {
   std::vector<Conv> convs;  // parameter order
@@ -110,6 +111,12 @@ int wgrad_chunks(const dmnet_desc& d, const Conv& c, int n) {
   return (int)((n * hw + kWgradChunk - 1) / kWgradChunk);
 }
 
+// chunks of the vector-unit weight and bias gradients of conv c at n samples
+int vgrad_chunks(const dmnet_desc& d, const Conv& c, int n) {
+  const long hw = (long)(d.size >> c.level) * (d.size >> c.level);
+  return (int)((n * hw + kVGradChunk - 1) / kVGradChunk);
+}
+
 constexpr int kMseBlocks = 256;
 
 NetLayout net_layout(const dmnet_desc& d, const Shape& s, const ActLayout& a) {
@@ -128,10 +135,14 @@ NetLayout net_layout(const dmnet_desc& d, const Shape& s, const ActLayout& a) {
   L.v = take(s.n_params * 4);
   L.acts = take(a.total * 4 * d.batch);
   L.grad_acts = take(a.total * 4 * d.batch);
+  // chunk partials of the weight and bias gradients (one conv at a time)
   size_t wpart = 1;
-  for (const Conv& c : s.convs)
+  for (const Conv& c : s.convs) {
     if (c.k == 3)
       wpart = std::max(wpart, (size_t)wgrad_chunks(d, c, d.batch) * c.cout * c.cin * 9);
+    wpart = std::max(wpart, (size_t)vgrad_chunks(d, c, d.batch) * c.cout *
+                                (1 + (size_t)c.cin * c.k * c.k));
+  }
   L.wpart = take(wpart * 4);
   L.partial = take(kMseBlocks * 4);
   L.loss = take(4);
@@ -276,9 +287,13 @@ dm_status conv_bwd(dmnet* net, const Conv& c, const float* x, long x_ns, const f
     hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(cnt)), dim3(256), 0, net->stream, part,
                        nch, cnt, dw);
     NET_LAUNCHED(net, "k_sum_chunks");
-    hipLaunchKernelGGL(dmn::k_bias_grad, dim3(c.cout), dim3(256), 0, net->stream, dz, z_ns,
-                       H * W, n, db);
+    const int bch = vgrad_chunks(net->d, c, n);
+    hipLaunchKernelGGL(dmn::k_bias_grad, dim3(c.cout, bch), dim3(256), 0, net->stream, dz,
+                       z_ns, H * W, n, kVGradChunk, part);
     NET_LAUNCHED(net, "k_bias_grad");
+    hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(c.cout)), dim3(256), 0, net->stream,
+                       part, bch, (long)c.cout, db);
+    NET_LAUNCHED(net, "k_sum_chunks (bias)");
     if (dx) {
       dim3 g((unsigned)(((long)n * H * W + 255) / 256), (c.cin + 31) / 32);
       hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, dz, c.cout, H, W,
@@ -287,16 +302,30 @@ dm_status conv_bwd(dmnet* net, const Conv& c, const float* x, long x_ns, const f
     }
     return DM_OK;
   }
-  if (c.k == 3) {
-    constexpr int CIB = 4;
-    hipLaunchKernelGGL((dmn::k_conv_wgrad<3, CIB>), dim3(c.cout, (c.cin + CIB - 1) / CIB),
-                       dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, z_ns, n, dw, db);
-  } else {
-    constexpr int CIB = 16;
-    hipLaunchKernelGGL((dmn::k_conv_wgrad<1, CIB>), dim3(c.cout, (c.cin + CIB - 1) / CIB),
-                       dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, z_ns, n, dw, db);
+  {
+    const int vch = vgrad_chunks(net->d, c, n);
+    float* part = net->f(net->L.wpart);
+    const long nw = (long)c.cout * c.cin * c.k * c.k;
+    float* bpart = part + (size_t)vch * nw;  // bias partials after the weight partials
+    if (c.k == 3) {
+      constexpr int CIB = 4;
+      hipLaunchKernelGGL((dmn::k_conv_wgrad<3, CIB>), dim3(c.cout, (c.cin + CIB - 1) / CIB, vch),
+                         dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, z_ns, n,
+                         kVGradChunk, part, bpart);
+    } else {
+      constexpr int CIB = 16;
+      hipLaunchKernelGGL((dmn::k_conv_wgrad<1, CIB>), dim3(c.cout, (c.cin + CIB - 1) / CIB, vch),
+                         dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, z_ns, n,
+                         kVGradChunk, part, bpart);
+    }
+    NET_LAUNCHED(net, "k_conv_wgrad");
+    hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(nw)), dim3(256), 0, net->stream, part,
+                       vch, nw, dw);
+    NET_LAUNCHED(net, "k_sum_chunks (weights)");
+    hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(c.cout)), dim3(256), 0, net->stream,
+                       bpart, vch, (long)c.cout, db);
+    NET_LAUNCHED(net, "k_sum_chunks (bias)");
   }
-  NET_LAUNCHED(net, "k_conv_wgrad");
   if (dx) {
     const int HW = H * W;
     const int bs = std::min(256, HW);

@@ -77,32 +77,37 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ x, int x
 }
 
 // ---------------------------------------------------------------------------
-// Weight and bias gradient of a convolution:
-//   dw[o][c][t] = sum_n sum_p dz[n][o][p] x[n][c][p + off_t]
-//   db[o]       = sum_n sum_p dz[n][o][p]                (block row 0 only)
-// One block per (o, chunk of CIB input channels); each thread sums a strided
-// subset of positions, then the block adds the per-thread sums in thread
-// order.  grid (zc, ceil(xc / CIB)), 256 threads.
+// Weight and bias gradient of a convolution over one chunk of positions:
+//   dwp[z][o][c][t] = sum_{(n, p) in chunk z} dz[n][o][p] x[n][c][p + off_t]
+//   dbp[z][o]       = sum_{(n, p) in chunk z} dz[n][o][p]   (block row 0 only)
+// (positions n * H*W + p in chunks of `chunk`); the chunk partials are then
+// added in chunk order (k_sum_chunks).  One block per (o, group of CIB input
+// channels, chunk); each thread sums a strided subset of the chunk's
+// positions, then the block adds the per-thread sums in thread order.
+// grid (zc, ceil(xc / CIB), n_chunks), 256 threads.
 // ---------------------------------------------------------------------------
 template <int K, int CIB>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x, int xc, int H,
                                                     int W, long x_ns, const float* __restrict__ dz,
-                                                    long z_ns, int n_samples,
-                                                    float* __restrict__ dw,
-                                                    float* __restrict__ db) {
+                                                    long z_ns, int n_samples, int chunk,
+                                                    float* __restrict__ dwp,
+                                                    float* __restrict__ dbp) {
   constexpr int KK = K * K;
   constexpr int NV = CIB * KK + 1;
   __shared__ float red[NV][257];
   const int HW = H * W;
+  const int zc = gridDim.x;
   const int o = blockIdx.x;
   const int c0 = blockIdx.y * CIB;
+  const int z = blockIdx.z;
   const int t = threadIdx.x;
   float acc[CIB * KK];
   float accb = 0.f;
 #pragma unroll
   for (int q = 0; q < CIB * KK; ++q) acc[q] = 0.f;
   const int total = n_samples * HW;
-  for (int pos = t; pos < total; pos += 256) {
+  const int p0 = z * chunk, p1 = min(total, p0 + chunk);
+  for (int pos = p0 + t; pos < p1; pos += 256) {
     const int n = pos / HW, p = pos % HW;
     const int i = p / W, j = p % W;
     const float g = dz[(long)n * z_ns + (long)o * HW + p];
@@ -128,10 +133,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x,
     float s = 0.f;
     for (int k = 0; k < 256; ++k) s += red[q][k];
     if (q == NV - 1) {
-      if (db && blockIdx.y == 0) db[o] = s;
+      if (dbp && blockIdx.y == 0) dbp[(long)z * zc + o] = s;
     } else {
       const int ci = q / KK, tt = q % KK;
-      if (c0 + ci < xc) dw[((long)o * xc + c0 + ci) * KK + tt] = s;
+      if (c0 + ci < xc) dwp[(((long)z * zc + o) * xc + c0 + ci) * KK + tt] = s;
     }
   }
 }
@@ -315,14 +320,17 @@ __global__ void k_sum_chunks(const float* __restrict__ part, int n_chunks, long 
   }
 }
 
-// db[o] = sum over samples and pixels of dz[o]; one block per o, the 256
-// per-thread sums added in thread order
+// dbp[z][o] = sum over the positions of chunk z of dz[o] (positions
+// n * H*W + p in chunks of `chunk`); one block per (o, chunk), the 256
+// per-thread sums added in thread order.  grid (zc, n_chunks)
 __global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dz, long z_ns,
-                                                   int HW, int n, float* __restrict__ db) {
+                                                   int HW, int n, int chunk,
+                                                   float* __restrict__ dbp) {
   __shared__ float red[256];
-  const int o = blockIdx.x;
+  const int o = blockIdx.x, z = blockIdx.y;
+  const int p0 = z * chunk, p1 = min(n * HW, p0 + chunk);
   float s = 0.f;
-  for (int P = threadIdx.x; P < n * HW; P += 256) {
+  for (int P = p0 + threadIdx.x; P < p1; P += 256) {
     const int sample = P / HW, p = P - sample * HW;
     s += dz[(long)sample * z_ns + (long)o * HW + p];
   }
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(256) void k_bias_grad(const float* __restrict__ dz,
   if (threadIdx.x == 0) {
     float t = 0.f;
     for (int i = 0; i < 256; ++i) t += red[i];
-    db[o] = t;
+    dbp[(long)z * gridDim.x + o] = t;
   }
 }
 

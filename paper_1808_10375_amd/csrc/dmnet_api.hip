@@ -102,7 +102,8 @@ ActLayout act_layout(const dmnet_desc& d, const Shape& s) {
 }
 
 struct NetLayout {
-  size_t params, wb, wbT, grads, m, v, acts, grad_acts, wpart, partial, loss, total;
+  size_t params, wb, wbT, wbK, wTK, grads, m, v, acts, grad_acts, xcl, wpart, partial, loss,
+      total;
 };
 
 // chunks of the matrix-core weight gradient of conv c at n samples
@@ -130,11 +131,22 @@ NetLayout net_layout(const dmnet_desc& d, const Shape& s, const ActLayout& a) {
   L.params = take(s.n_params * 4);
   L.wb = take(s.n_params * 2);
   L.wbT = take(s.n_params * 2);  // flipped, transposed 3x3 weights (data gradient)
+  L.wbK = take(s.n_params * 2);  // tap-major 3x3 weights [o][t][c]
+  L.wTK = take(s.n_params * 2);  // tap-major flipped, transposed [c][t][o]
   L.grads = take(s.n_params * 4);
   L.m = take(s.n_params * 4);
   L.v = take(s.n_params * 4);
   L.acts = take(a.total * 4 * d.batch);
   L.grad_acts = take(a.total * 4 * d.batch);
+  // channel-last bfloat16 copy of a 3x3 convolution's input (or output
+  // gradient), one convolution at a time
+  size_t xcl = 8;
+  for (const Conv& c : s.convs)
+    if (c.k == 3) {
+      const size_t hw = (size_t)(d.size >> c.level) * (d.size >> c.level);
+      xcl = std::max(xcl, (size_t)d.batch * hw * std::max(c.cin, c.cout));
+    }
+  L.xcl = take(xcl * 2);
   // chunk partials of the weight and bias gradients (one conv at a time)
   size_t wpart = 1;
   for (const Conv& c : s.convs) {
@@ -166,6 +178,9 @@ struct dmnet {
   float* params() { return f(L.params); }
   uint16_t* wb() { return reinterpret_cast<uint16_t*>(ws + L.wb); }
   uint16_t* wbT() { return reinterpret_cast<uint16_t*>(ws + L.wbT); }
+  uint16_t* wbK() { return reinterpret_cast<uint16_t*>(ws + L.wbK); }
+  uint16_t* wTK() { return reinterpret_cast<uint16_t*>(ws + L.wTK); }
+  uint16_t* xcl() { return reinterpret_cast<uint16_t*>(ws + L.xcl); }
   bool mfma() const { return !(d.flags & DMNET_FLAG_FP32_WEIGHTS); }
   float* grads() { return f(L.grads); }
   float* act(size_t o) { return f(L.acts) + o; }     // per-sample stride a.total
@@ -219,6 +234,9 @@ dm_status refresh_transposed(dmnet* net) {
     const long cnt = (long)c.cout * c.cin * 9;
     hipLaunchKernelGGL(dmn::k_flip_transpose3, dim3(grid_for(cnt)), dim3(256), 0, net->stream,
                        net->wb() + c.w_off, c.cout, c.cin, net->wbT() + c.w_off);
+    hipLaunchKernelGGL(dmn::k_tapmajor3, dim3(grid_for(cnt)), dim3(256), 0, net->stream,
+                       net->wb() + c.w_off, c.cout, c.cin, net->wbK() + c.w_off,
+                       net->wTK() + c.w_off);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -239,6 +257,18 @@ dm_status conv_fwd(dmnet* net, const Conv& c, const float* x, long x_ns, float* 
   const int HW = H * W;
   if (net->mfma() && c.k == 3) {
     dim3 g((unsigned)(((long)n * HW + 255) / 256), (c.cout + 31) / 32);
+    if (c.cin % 32 == 0 && c.w_off % 8 == 0) {
+      // channel-last bfloat16 copy of the input, then 16-byte operand loads
+      // (the weight rows start 16-byte aligned)
+      const long cnt = (long)n * HW * (c.cin / 8);
+      hipLaunchKernelGGL(dmn::k_to_cl_bf16, dim3(grid_for(cnt)), dim3(256), 0, net->stream, x,
+                         c.cin, HW, x_ns, n, net->xcl());
+      NET_LAUNCHED(net, "k_to_cl_bf16");
+      hipLaunchKernelGGL(dmn::k_conv3_mfma_cl, g, dim3(256), 0, net->stream, net->xcl(), c.cin,
+                         H, W, n, net->wbK() + c.w_off, b, y, c.cout, y_ns, relu ? 1 : 0);
+      NET_LAUNCHED(net, "k_conv3_mfma_cl");
+      return DM_OK;
+    }
     hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, n,
                        wb, b, y, c.cout, y_ns, relu ? 1 : 0);
     NET_LAUNCHED(net, "k_conv3_mfma");
@@ -296,9 +326,19 @@ dm_status conv_bwd(dmnet* net, const Conv& c, const float* x, long x_ns, const f
     NET_LAUNCHED(net, "k_sum_chunks (bias)");
     if (dx) {
       dim3 g((unsigned)(((long)n * H * W + 255) / 256), (c.cin + 31) / 32);
-      hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, dz, c.cout, H, W,
-                         z_ns, n, net->wbT() + c.w_off, nullptr, dx, c.cin, dx_ns, 0);
-      NET_LAUNCHED(net, "k_conv3_mfma (data gradient)");
+      if (c.cout % 32 == 0 && c.w_off % 8 == 0) {
+        const long cnt = (long)n * H * W * (c.cout / 8);
+        hipLaunchKernelGGL(dmn::k_to_cl_bf16, dim3(grid_for(cnt)), dim3(256), 0, net->stream,
+                           dz, c.cout, H * W, z_ns, n, net->xcl());
+        NET_LAUNCHED(net, "k_to_cl_bf16 (output gradient)");
+        hipLaunchKernelGGL(dmn::k_conv3_mfma_cl, g, dim3(256), 0, net->stream, net->xcl(),
+                           c.cout, H, W, n, net->wTK() + c.w_off, nullptr, dx, c.cin, dx_ns, 0);
+        NET_LAUNCHED(net, "k_conv3_mfma_cl (data gradient)");
+      } else {
+        hipLaunchKernelGGL(dmn::k_conv3_mfma, g, dim3(256), 0, net->stream, dz, c.cout, H, W,
+                           z_ns, n, net->wbT() + c.w_off, nullptr, dx, c.cin, dx_ns, 0);
+        NET_LAUNCHED(net, "k_conv3_mfma (data gradient)");
+      }
     }
     return DM_OK;
   }

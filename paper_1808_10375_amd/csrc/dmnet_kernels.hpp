@@ -242,6 +242,124 @@ __global__ __launch_bounds__(256) void k_conv3_mfma(const float* __restrict__ x,
   }
 }
 
+// x (float32 [n][C][H*W], sample stride x_ns) -> bfloat16 channel-last
+// xs[n][H*W][C] (round to nearest even), C a multiple of 8.  One thread per
+// (8 channels, pixel), pixels fastest: the reads of a wave are consecutive
+// pixels of one channel, each write is 16 bytes.
+__global__ void k_to_cl_bf16(const float* __restrict__ x, int C, int HW, long x_ns, int n,
+                             uint16_t* __restrict__ xs) {
+  const long np = (long)n * HW;
+  const long total = np * (C / 8);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long P = e % np;
+    const int c8 = (int)(e / np);
+    const int smp = (int)(P / HW), p = (int)(P - (long)smp * HW);
+    const float* __restrict__ src = x + (long)smp * x_ns + (long)(c8 * 8) * HW + p;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = (uint32_t)f_to_bf16_bits(src[(long)(2 * q) * HW]) |
+             ((uint32_t)f_to_bf16_bits(src[(long)(2 * q + 1) * HW]) << 16);
+    *reinterpret_cast<uint4*>(xs + P * C + c8 * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// y[o][P] = b[o] + sum_{t, c} A2[o][t][c] xs[P + off_t][c] over the 3 x 3 taps t
+// (zero padding), optional ReLU: the same convolution as k_conv3_mfma with
+// a channel-last bfloat16 input xs[n][H][W][xc] (xc a multiple of 32) and
+// tap-major weights A2 [yc][9][xc].  K = 9 xc runs in steps of 32 that are
+// one tap and 32 channels, so each lane's 8 values of an operand fragment
+// are 8 consecutive channels: one 16-byte load.  With A2 the flipped,
+// transposed weights and xs the output gradient this is the data gradient.
+// Block: 4 waves; tile 32 output channels x 256 pixels (64 per wave).
+// grid (ceil(n H W / 256), ceil(yc / 32))
+__global__ __launch_bounds__(256) void k_conv3_mfma_cl(const uint16_t* __restrict__ xs, int xc,
+                                                       int H, int W, int n,
+                                                       const uint16_t* __restrict__ A2,
+                                                       const float* __restrict__ bias,
+                                                       float* __restrict__ y, int yc, long y_ns,
+                                                       int relu) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int HW = H * W, NP = n * HW, K = xc * 9;
+  const int o0 = blockIdx.y * 32;
+  const int pw = blockIdx.x * 256 + wave * 64;
+  int smp[4], pi[4], pj[4];
+  bool pok[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int P = pw + 16 * ct + (lane & 15);
+    pok[ct] = P < NP;
+    const int Pc = pok[ct] ? P : 0;
+    smp[ct] = Pc / HW;
+    const int p = Pc - smp[ct] * HW;
+    pi[ct] = p / W;
+    pj[ct] = p - pi[ct] * W;
+  }
+  const int q8 = 8 * (lane >> 4);
+  const nb_s16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  nb_f32x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int t = k0 / xc;
+    const int c = k0 - t * xc + q8;
+    const int dy = t / 3 - 1, dx = t - 3 * (t / 3) - 1;
+    nb_s16x8 a[2], b[4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int o = o0 + 16 * rt + (lane & 15);
+      a[rt] = (o < yc) ? *reinterpret_cast<const nb_s16x8*>(A2 + (long)o * K + k0 + q8) : zero8;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int ii = pi[ct] + dy, jj = pj[ct] + dx;
+      const bool ok = pok[ct] && (unsigned)ii < (unsigned)H && (unsigned)jj < (unsigned)W;
+      b[ct] = ok ? *reinterpret_cast<const nb_s16x8*>(
+                       xs + (((long)smp[ct] * H + ii) * W + jj) * xc + c)
+                 : zero8;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_mma(a[rt], b[ct], acc[rt][ct]);
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    if (!pok[ct]) continue;
+    const int p = pi[ct] * W + pj[ct];
+    float* __restrict__ yn = y + (long)smp[ct] * y_ns;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + 16 * rt + 4 * (lane >> 4) + r;
+        if (o < yc) {
+          float v = acc[rt][ct][r] + (bias ? bias[o] : 0.f);
+          yn[(long)o * HW + p] = relu ? fmaxf(v, 0.f) : v;
+        }
+      }
+  }
+}
+
+// Tap-major copies of the bfloat16 3 x 3 weights w[o][c][t] (yc x xc):
+// wK[o][t][c] = w[o][c][t] (forward) and wTK[c][8 - t][o] = w[o][c][t]
+// (data gradient: flipped, transposed)
+__global__ void k_tapmajor3(const uint16_t* __restrict__ w, int yc, int xc,
+                            uint16_t* __restrict__ wK, uint16_t* __restrict__ wTK) {
+  const long total = (long)yc * xc * 9;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(e % 9);
+    const long oc = e / 9;
+    const int c = (int)(oc % xc), o = (int)(oc / xc);
+    wK[((long)o * 9 + t) * xc + c] = w[e];
+    wTK[((long)c * 9 + (8 - t)) * yc + o] = w[e];
+  }
+}
+
 // Weight gradient of a 3x3 convolution over one chunk of pixels:
 //   part[chunk][o][k] = sum_{P in chunk} dz[o][P] im2col(x)[k][P]
 // GEMM rows o (zc), columns k (xc * 9), reduction over P in steps of 32.

@@ -102,8 +102,8 @@ ActLayout act_layout(const dmnet_desc& d, const Shape& s) {
 }
 
 struct NetLayout {
-  size_t params, wb, wbT, wbK, wTK, grads, m, v, acts, grad_acts, xcl, wpart, partial, loss,
-      total;
+  size_t params, wb, wbT, wbK, wTK, grads, m, v, acts, grad_acts, xcl, wgb, wpart, partial,
+      loss, total;
 };
 
 // chunks of the matrix-core weight gradient of conv c at n samples
@@ -147,6 +147,15 @@ NetLayout net_layout(const dmnet_desc& d, const Shape& s, const ActLayout& a) {
       xcl = std::max(xcl, (size_t)d.batch * hw * std::max(c.cin, c.cout));
     }
   L.xcl = take(xcl * 2);
+  // bfloat16 copies for a 3x3 weight gradient: the input shifted by each
+  // column offset (3 copies) and the output gradient
+  size_t wgb = 8;
+  for (const Conv& c : s.convs)
+    if (c.k == 3) {
+      const size_t hw = (size_t)(d.size >> c.level) * (d.size >> c.level);
+      wgb = std::max(wgb, (size_t)d.batch * hw * (3 * (size_t)c.cin + c.cout));
+    }
+  L.wgb = take(wgb * 2);
   // chunk partials of the weight and bias gradients (one conv at a time)
   size_t wpart = 1;
   for (const Conv& c : s.convs) {
@@ -181,6 +190,7 @@ struct dmnet {
   uint16_t* wbK() { return reinterpret_cast<uint16_t*>(ws + L.wbK); }
   uint16_t* wTK() { return reinterpret_cast<uint16_t*>(ws + L.wTK); }
   uint16_t* xcl() { return reinterpret_cast<uint16_t*>(ws + L.xcl); }
+  uint16_t* wgb() { return reinterpret_cast<uint16_t*>(ws + L.wgb); }
   bool mfma() const { return !(d.flags & DMNET_FLAG_FP32_WEIGHTS); }
   float* grads() { return f(L.grads); }
   float* act(size_t o) { return f(L.acts) + o; }     // per-sample stride a.total
@@ -309,10 +319,25 @@ dm_status conv_bwd(dmnet* net, const Conv& c, const float* x, long x_ns, const f
     const int K = c.cin * 9;
     const int nch = wgrad_chunks(net->d, c, n);
     float* part = net->f(net->L.wpart);
-    hipLaunchKernelGGL(dmn::k_conv3_wgrad_mfma, dim3((K + 255) / 256, (c.cout + 31) / 32, nch),
-                       dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, dz, c.cout, z_ns, n,
-                       kWgradChunk, part);
-    NET_LAUNCHED(net, "k_conv3_wgrad_mfma");
+    const dim3 wg((K + 255) / 256, (c.cout + 31) / 32, nch);
+    if (W % 8 == 0) {
+      // bfloat16 copies: x shifted by each column offset, and dz
+      uint16_t* xs3 = net->wgb();
+      uint16_t* dzb = xs3 + (size_t)3 * n * c.cin * H * W;
+      hipLaunchKernelGGL(dmn::k_to_bf16_shift3, dim3(grid_for((long)n * c.cin * H * W)),
+                         dim3(256), 0, net->stream, x, c.cin, H, W, x_ns, n, xs3);
+      NET_LAUNCHED(net, "k_to_bf16_shift3");
+      hipLaunchKernelGGL(dmn::k_to_bf16_nchw, dim3(grid_for((long)n * c.cout * H * W)),
+                         dim3(256), 0, net->stream, dz, c.cout, H * W, z_ns, n, dzb);
+      NET_LAUNCHED(net, "k_to_bf16_nchw");
+      hipLaunchKernelGGL(dmn::k_conv3_wgrad_mfma_s, wg, dim3(256), 0, net->stream, xs3, c.cin,
+                         H, W, dzb, c.cout, n, kWgradChunk, part);
+      NET_LAUNCHED(net, "k_conv3_wgrad_mfma_s");
+    } else {
+      hipLaunchKernelGGL(dmn::k_conv3_wgrad_mfma, wg, dim3(256), 0, net->stream, x, c.cin, H,
+                         W, x_ns, dz, c.cout, z_ns, n, kWgradChunk, part);
+      NET_LAUNCHED(net, "k_conv3_wgrad_mfma");
+    }
     const long cnt = (long)c.cout * K;
     hipLaunchKernelGGL(dmn::k_sum_chunks, dim3(grid_for(cnt)), dim3(256), 0, net->stream, part,
                        nch, cnt, dw);

@@ -344,6 +344,120 @@ __global__ __launch_bounds__(256) void k_conv3_mfma_cl(const uint16_t* __restric
   }
 }
 
+// bfloat16 copies for the weight gradient (round to nearest even):
+//   xs3[d][n][C][H][W] = x[n][C][i][j + d - 1] (0 outside), d = 0, 1, 2
+// the input shifted by each column offset of the 3 x 3 taps, so that 8
+// consecutive output pixels of a row read 8 consecutive, 16-byte aligned
+// values for every tap; x float32 [n][C][H*W], sample stride x_ns.
+__global__ void k_to_bf16_shift3(const float* __restrict__ x, int C, int H, int W, long x_ns,
+                                 int n, uint16_t* __restrict__ xs3) {
+  const long per = (long)n * C * H * W;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < per;
+       e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % W);
+    const long r = e / W;  // (s * C + c) * H + i
+    const int i = (int)(r % H);
+    const long sc = r / H;
+    const int c = (int)(sc % C), smp = (int)(sc / C);
+    const float* __restrict__ row = x + (long)smp * x_ns + ((long)c * H + i) * W;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int jj = j + d - 1;
+      xs3[(long)d * per + e] = ((unsigned)jj < (unsigned)W) ? f_to_bf16_bits(row[jj]) : 0;
+    }
+  }
+}
+
+// dz float32 [n][C][HW] (sample stride z_ns) -> bfloat16 [n][C][HW]
+__global__ void k_to_bf16_nchw(const float* __restrict__ dz, int C, int HW, long z_ns, int n,
+                               uint16_t* __restrict__ out) {
+  const long per = (long)C * HW, total = per * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int smp = (int)(e / per);
+    out[e] = f_to_bf16_bits(dz[(long)smp * z_ns + (e - (long)smp * per)]);
+  }
+}
+
+// Weight gradient of a 3x3 convolution over one chunk of pixels from the
+// bfloat16 copies above (same sums as k_conv3_wgrad_mfma):
+//   part[chunk][o][k] = sum_{P in chunk} dz[o][P] im2col(x)[k][P],  k = c*9 + t
+// A fragment: 8 consecutive pixels of one output channel of dzb; B fragment:
+// 8 consecutive pixels of one (c, t) from the shifted copy of its column
+// offset, rows outside the image read as zero.  W must be a multiple of 8
+// and chunk a multiple of 32.  Block: 4 waves; tile 32 o x 256 k.
+// grid (ceil(K / 256), ceil(zc / 32), n_chunks)
+__global__ __launch_bounds__(256) void k_conv3_wgrad_mfma_s(
+    const uint16_t* __restrict__ xs3, int xc, int H, int W, const uint16_t* __restrict__ dzb,
+    int zc, int n, int chunk, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int HW = H * W, NP = n * HW, K = xc * 9;
+  const long per = (long)n * xc * HW;  // one shifted copy
+  const int o0 = blockIdx.y * 32;
+  const int kw = blockIdx.x * 256 + wave * 64;
+  const int P0 = blockIdx.z * chunk, P1 = min(NP, P0 + chunk);
+  const nb_s16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  // the (channel, tap) of each of this lane's four B columns
+  int bc[4], bdy[4];
+  long bbase[4];
+  bool bok[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int k = kw + 16 * ct + (lane & 15);
+    bok[ct] = k < K;
+    const int kc = bok[ct] ? k : 0;
+    bc[ct] = kc / 9;
+    const int t = kc - 9 * bc[ct];
+    bdy[ct] = t / 3 - 1;
+    bbase[ct] = (long)(t - 3 * (t / 3)) * per;  // shifted copy of the tap's column offset
+  }
+  nb_f32x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int Ps = P0; Ps < P1; Ps += 32) {
+    const int Pb = Ps + 8 * (lane >> 4);  // 8 consecutive pixels of one row
+    const bool in = Pb < P1;
+    const int smp = in ? Pb / HW : 0;
+    const int p = in ? Pb - smp * HW : 0;
+    const int i = p / W, j = p - (p / W) * W;
+    nb_s16x8 a[2], b[4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int o = o0 + 16 * rt + (lane & 15);
+      a[rt] = (in && o < zc)
+                  ? *reinterpret_cast<const nb_s16x8*>(dzb + ((long)smp * zc + o) * HW + p)
+                  : zero8;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int ii = i + bdy[ct];
+      const bool ok = in && bok[ct] && (unsigned)ii < (unsigned)H;
+      b[ct] = ok ? *reinterpret_cast<const nb_s16x8*>(
+                       xs3 + bbase[ct] + (((long)smp * xc + bc[ct]) * H + ii) * W + j)
+                 : zero8;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = nb_mma(a[rt], b[ct], acc[rt][ct]);
+  }
+  float* __restrict__ pc = part + (long)blockIdx.z * zc * K;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int k = kw + 16 * ct + (lane & 15);
+      if (k >= K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + 16 * rt + 4 * (lane >> 4) + r;
+        if (o < zc) pc[(long)o * K + k] = acc[rt][ct][r];
+      }
+    }
+}
+
 // Tap-major copies of the bfloat16 3 x 3 weights w[o][c][t] (yc x xc):
 // wK[o][t][c] = w[o][c][t] (forward) and wTK[c][8 - t][o] = w[o][c][t]
 // (data gradient: flipped, transposed)

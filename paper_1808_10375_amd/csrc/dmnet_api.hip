@@ -524,12 +524,9 @@ dm_status loss_and_grad(dmnet* net, const float* x, const float* target, int n) 
   // the outputs of the n samples sit T floats apart: one block per sample,
   // each leaving its sum of squares in partial[k]; the loss averages over
   // all n * per outputs
-  for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(dmn::k_mse, dim3(1), dim3(256), 0, net->stream, net->act(a.y) + k * T,
-                       target + k * per, per, (float)(per * n), net->gact(a.y) + k * T,
-                       net->f(net->L.partial) + k);
-    NET_LAUNCHED(net, "k_mse");
-  }
+  hipLaunchKernelGGL(dmn::k_mse, dim3(n), dim3(256), 0, net->stream, net->act(a.y), T, target,
+                     per, per, (float)(per * n), net->gact(a.y), T, net->f(net->L.partial));
+  NET_LAUNCHED(net, "k_mse");
   return DM_OK;
 }
 

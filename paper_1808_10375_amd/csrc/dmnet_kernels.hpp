@@ -541,13 +541,22 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad_mfma(
     }
 }
 
-// dw[e] = sum over chunks of part[chunk][e], in chunk order
+// dw[e] = sum over chunks of part[chunk][e], in chunk order (loads issued
+// eight chunks at a time)
 __global__ void k_sum_chunks(const float* __restrict__ part, int n_chunks, long count,
                              float* __restrict__ dw) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
        e += (long)gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int c = 0; c < n_chunks; ++c) s += part[(long)c * count + e];
+    int c = 0;
+    for (; c + 8 <= n_chunks; c += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(long)(c + q) * count + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; c < n_chunks; ++c) s += part[(long)c * count + e];
     dw[e] = s;
   }
 }
@@ -666,19 +675,25 @@ __global__ void k_relu_mask(float* __restrict__ g, long g_ns, const float* __res
   }
 }
 
-// dy = 2 (y - t) / denom over count elements, and per-block partial sums of
-// (y - t)^2 (denom: number of outputs the loss averages over)
-__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
-                                             const float* __restrict__ t, long count,
-                                             float denom, float* __restrict__ dy,
+// dy = 2 (y - t) / denom over the count outputs of each sample, and the
+// per-sample sums of (y - t)^2 in partial[] (denom: number of outputs the
+// loss averages over); grid: one block per sample
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, long y_ns,
+                                             const float* __restrict__ t, long t_ns, long count,
+                                             float denom, float* __restrict__ dy, long dy_ns,
                                              float* __restrict__ partial) {
+  // one block per sample: sample k's outputs at y + k y_ns (count values)
   __shared__ float red[256];
+  const int smp = blockIdx.x;
+  const float* __restrict__ ys = y + (long)smp * y_ns;
+  const float* __restrict__ ts = t + (long)smp * t_ns;
+  float* __restrict__ ds = dy + (long)smp * dy_ns;
   float s = 0.f;
   const float k = 2.0f / denom;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < count; e += (long)gridDim.x * 256) {
-    const float d = y[e] - t[e];
+  for (long e = threadIdx.x; e < count; e += 256) {
+    const float d = ys[e] - ts[e];
     s += d * d;
-    dy[e] = k * d;
+    ds[e] = k * d;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -686,7 +701,7 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y,
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[smp] = red[0];
 }
 
 __global__ void k_sum_partials(const float* __restrict__ partial, int n, long count,

@@ -508,27 +508,30 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
 //   pass 1  per mode: Z = 2 P O - psi, forward DFT, mode sum S += |Z~|^2,
 //           Z~ -> scratch
 //   scale   g = sqrt(I / S) / F^2 (definition of F_c)
-//   pass 2  per mode, last mode first (in the merged form with V = 1 its
-//           spectrum never leaves the registers): Z~ from scratch, times g, inverse DFT; with MERGE the
-//           view update psi' = psi + beta (Z' - P O) (Eq. 3) and the object
-//           numerator sum_k conj(P_k) psi'_k follow at once, otherwise Z'
-//           goes back to scratch and
+//   pass 2  per mode, last mode first (in the merged form with V = 1 the
+//           last spectrum never leaves the registers): Z~ from scratch,
+//           times g, inverse DFT; with MERGE the view update
+//           psi' = psi + beta (Z' - P O) (Eq. 3) and the object numerator
+//           sum_k conj(P_k) psi'_k follow at once, otherwise Z' goes back to
+//           scratch and
 //   pass 3  per mode: Z' from scratch, the view update and the numerator
 //           (no transform runs while the numerator is live)
 // Every mode is transformed twice (no recomputation); psi is written once
 // and read once or twice, with the non-temporal hint (NT) so the probe and
-// the object stay in L2 (the merged form with the eps_psi partials reads psi
-// through the caches in pass 1 and streams the slot instead).  The merged form without PSI_ERR never reads psi
-// in pass 2: since psi = 2 P O - Z and the transforms are linear,
+// the object stay in L2 (the merged form with the eps_psi partials reads
+// psi through the caches in pass 1 and streams the slot instead).
+// The merged form without PSI_ERR never reads psi in pass 2: since
+// psi = 2 P O - Z and the transforms are linear,
 //   psi' = psi + beta (Z' - P O) = (2 - beta) P O + F^-1[(beta g - 1/F^2) Z~]
 // (the unnormalised inverse of the spectrum scaled by beta g - 1/F^2 is
 // beta Z' - Z), so one inverse transform gives psi' directly.  What it
 // cannot give is psi' - psi, so the eps_psi partial sums are left at zero;
-// with PSI_ERR the update reads psi again and forms them.  A thread runs V virtual threads of the transform (F*F/(16 V)
-// threads).  With V = 1 (128 registers a thread) the merged form parks the
-// scale to make room for the numerator: the rows that fit beside the
-// exchange buffer in LDS, the rest in the slot; with V = 2 (256 registers)
-// the scale and the numerator both stay in registers.
+// with PSI_ERR the update reads psi again and forms them.
+// A thread runs V virtual threads of the transform (F*F/(16 V) threads).
+// With V = 1 (128 registers a thread) the merged form parks the scale to
+// make room for the numerator: the rows that fit beside the exchange buffer
+// in LDS, the rest in the slot; with V = 2 (256 registers) the scale and the
+// numerator both stay in registers.
 // ---------------------------------------------------------------------------
 template <int F, int V, bool NT_HINT, bool MERGE, bool PSI_ERR = true>
 __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(

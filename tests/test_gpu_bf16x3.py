@@ -120,3 +120,24 @@ def test_bf16x3_error_history_tracks_fp32_path():
         f"max rel deviation {dev_rel.max():.2e}")
     assert np.all(np.isfinite(hist["bf16x3"]))
     assert dev_rel[-1] <= 0.05 and np.median(dev_rel) <= 0.05
+
+
+def test_bf16x3_full_size_one_step_against_fp64():
+    """The 2500-view, 5-mode, 128x128 scan at full size, one step of the
+    BF16x3 form from the initial views, against the FP64 oracle: the form's
+    error is stated and bounded by 1e-4 (the exact-sum emulation is too slow
+    at this size; the 300-view subset above checks it)."""
+    s = synth.multimode_spiral_128(1)
+    say("case bf16x3 full size: 2500 views x 5 modes x 128^2, one step")
+    psi0 = oracle.init_views(s.P0, s.O0, s.pos)
+    P0, O0 = s.P0.astype(np.complex128), s.O0.astype(np.complex128)
+    psi_x, P_x, O_x, e_x = oracle.iterate(psi0, P0, O0, s.pos, s.I.astype(np.float64), 0.8)
+    den = oracle.object_update(psi_x, P0, O0, s.pos)[1]
+    psi_g, P_g, O_g, e_g, it = gpu_steps(dict(I=s.I, P=s.P0, O=s.O0, pos=s.pos, beta=0.8,
+                                              psi=psi0.astype(np.complex64)))
+    assert it == 1
+    f64 = (rel(psi_g, psi_x), rel(O_g, O_x, den), rel(P_g, P_x))
+    say(f"  vs FP64: psi {f64[0]:.2e} O(w) {f64[1]:.2e} P {f64[2]:.2e} | "
+        f"eps_P gpu {e_g['eps_probe']:.6e} fp64 {e_x['eps_probe']:.6e}")
+    assert max(f64) <= FP64_TOL, f64
+    assert abs(e_g["eps_probe"] - e_x["eps_probe"]) <= 1e-3 * e_x["eps_probe"]

@@ -151,20 +151,38 @@ __global__ __launch_bounds__(256) void k_mf_rows_fwd(const ScanDev* __restrict__
         re[rt][nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
         im[rt][nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
       }
-    for (int ks = 0; ks < kMfKs; ++ks) {
-      MfA a[2];
+    // the raw loads of k step ks + 1 go out before the products of step ks
+    float2 pv[2][8], ov[2][8], sv[2][8];
+    auto load_step = [&](int ks) {
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
         const int row = 32 * wave + 16 * rt + (lane & 15);
         const int k0 = 32 * ks + 8 * (lane >> 4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          pv[rt][e] = P[row * F + k0 + e];
+          ov[rt][e] = O[(size_t)row * W + k0 + e];
+          sv[rt][e] = psi[row * F + k0 + e];
+        }
+      }
+    };
+    load_step(0);
+#pragma unroll
+    for (int ks = 0; ks < kMfKs; ++ks) {
+      MfA a[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
         float2 z[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float2 phi = cmul(P[row * F + k0 + e], O[(size_t)row * W + k0 + e]);
-          const float2 ps = psi[row * F + k0 + e];
-          z[e] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
+          const float2 phi = cmul(pv[rt][e], ov[rt][e]);
+          z[e] = make_float2(2.f * phi.x - sv[rt][e].x, 2.f * phi.y - sv[rt][e].y);
         }
         a[rt] = mf_split_complex(z);
+      }
+      if (ks + 1 < kMfKs) {
+        load_step(ks + 1);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int nt = 0; nt < kMfNt; ++nt) {
@@ -222,12 +240,16 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
           ure[m][at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
           uim[m][at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
         }
-        for (int ks = 0; ks < kMfKs; ++ks) {
-          const int k0 = 32 * ks + 8 * (lane >> 4);
-          float2 z[8];
+        // all of this mode's column loads first: one memory latency per mode
+        float2 zall[kMfKs][8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) z[e] = Tm[(k0 + e) * F + n0 + (lane & 15)];
-          const MfA a = mf_split_complex(z);
+        for (int ks = 0; ks < kMfKs; ++ks)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            zall[ks][e] = Tm[(32 * ks + 8 * (lane >> 4) + e) * F + n0 + (lane & 15)];
+#pragma unroll
+        for (int ks = 0; ks < kMfKs; ++ks) {
+          const MfA a = mf_split_complex(zall[ks]);
 #pragma unroll
           for (int at = 0; at < 2; ++at) {
             const int nt = 2 * wave + at;
@@ -359,13 +381,16 @@ __global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__
         re[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
         im[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      for (int ks = 0; ks < kMfKs; ++ks) {
-        const int row = rbase + (lane & 15);
-        const int k0 = 32 * ks + 8 * (lane >> 4);
-        float2 z[8];
+      // all of this mode's row loads first: one memory latency per mode
+      float2 zall[kMfKs][8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) z[e] = V[row * F + k0 + e];
-        const MfA a = mf_split_complex(z);
+      for (int ks = 0; ks < kMfKs; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          zall[ks][e] = V[(rbase + (lane & 15)) * F + 32 * ks + 8 * (lane >> 4) + e];
+#pragma unroll
+      for (int ks = 0; ks < kMfKs; ++ks) {
+        const MfA a = mf_split_complex(zall[ks]);
 #pragma unroll
         for (int nt = 0; nt < kMfNt; ++nt)
           mf_cmma<true>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),

@@ -38,9 +38,10 @@ constexpr int kMfFrag = kMfKs * kMfNt * 64;  // uint4 per matrix
 constexpr int kMfWords = 4 * kMfFrag;        // uint4 of the whole table (128 KB)
 constexpr int kMfMaxModes = 8;
 
+// float -> bfloat16 bits, round to nearest even (the conversion gfx950 does
+// in hardware, two values per v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint32_t mf_bf16_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 // split 8 floats into packed bfloat16 hi and lo pieces (lo = bf16(x - hi))

@@ -630,7 +630,8 @@ dm_status launch_views_mfma(dm_ctx* c) {
   hipLaunchKernelGGL(dmk::k_mf_rows_fwd, dim3(mfma_grid(c, nv * M)), dim3(256), kMfLdsW,
                      c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
   DM_LAUNCHED(c, "k_mf_rows_fwd");
-  hipLaunchKernelGGL(dmk::k_mf_cols, dim3(mfma_grid(c, nv * dmk::kMfNt)), dim3(256), kMfLdsCols,
+  hipLaunchKernelGGL(dmk::k_mf_cols, dim3(mfma_grid(c, nv * dmk::kMfNt)),
+                     dim3(dmk::kMfColsThreads), kMfLdsCols,
                      c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
   DM_LAUNCHED(c, "k_mf_cols");
   hipLaunchKernelGGL(dmk::k_mf_rows_inv, dim3(mfma_grid(c, nv * 2)), dim3(256), kMfLdsW,

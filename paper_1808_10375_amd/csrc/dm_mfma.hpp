@@ -208,14 +208,19 @@ __global__ __launch_bounds__(256) void k_mf_rows_fwd(const ScanDev* __restrict__
 
 // ---------------------------------------------------------------------------
 // (2) column transform, modulus projection and inverse column transform for
-// 16 columns n0 .. n0+15 of every mode of one view, in place in T.
-//   U^T[n][a] = sum_k T[k][n] W[k][a]        (wave w: a-tiles 2w, 2w+1)
+// 16 columns n0 .. n0+15 of every mode of one view, in place in T.  Eight
+// waves (two per SIMD, so one's memory waits overlap the other's products);
+// wave w owns output tile w (rows a = 16 w .. 16 w + 15 of U^T, V^T).
+//   U^T[n][a] = sum_k T[k][n] W[k][a]
 //   U' = U * sqrt(I / sum_m |U_m|^2) / F^2
 //   V^T[n][a'] = sum_a U'^T[n][a] conj(W)[a][a']   (A operand via LDS)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ scans,
-                                                 const int2* __restrict__ vmap, int total_views,
-                                                 int M, const uint4* __restrict__ wf) {
+constexpr int kMfColsThreads = 512;
+
+__global__ __launch_bounds__(kMfColsThreads) void k_mf_cols(const ScanDev* __restrict__ scans,
+                                                            const int2* __restrict__ vmap,
+                                                            int total_views, int M,
+                                                            const uint4* __restrict__ wf) {
   extern __shared__ uint4 wl[];
   mf_load_w(wl, wf);
   // U' of one mode in A-fragment order: [mat][ks][lane] uint4, mat = re hi,
@@ -223,6 +228,7 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
   uint16_t* ua = reinterpret_cast<uint16_t*>(wl + kMfWords);
   constexpr int F = kMfF, FF = F * F;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = wave;  // this wave's 16 columns of the transform output
   const int total = total_views * kMfNt;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int2 vm = vmap[item / kMfNt];
@@ -231,16 +237,13 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
     const int j = uni(vm.y);
     float2* __restrict__ T = sc.tspec + (size_t)j * M * FF;
     const float* __restrict__ I = sc.I + (size_t)j * FF;
-    mf_f32x4 ure[kMfMaxModes][2], uim[kMfMaxModes][2];
+    mf_f32x4 ure[kMfMaxModes], uim[kMfMaxModes];
 #pragma unroll
     for (int m = 0; m < kMfMaxModes; ++m) {
       if (m < M) {
         const float2* __restrict__ Tm = T + (size_t)m * FF;
-#pragma unroll
-        for (int at = 0; at < 2; ++at) {
-          ure[m][at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-          uim[m][at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-        }
+        ure[m] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
+        uim[m] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
         // all of this mode's column loads first: one memory latency per mode
         float2 zall[kMfKs][8];
 #pragma unroll
@@ -251,66 +254,52 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
 #pragma unroll
         for (int ks = 0; ks < kMfKs; ++ks) {
           const MfA a = mf_split_complex(zall[ks]);
-#pragma unroll
-          for (int at = 0; at < 2; ++at) {
-            const int nt = 2 * wave + at;
-            mf_cmma<false>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
-                           mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), ure[m][at],
-                           uim[m][at]);
-          }
+          mf_cmma<false>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
+                         mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), ure[m], uim[m]);
         }
       }
     }
-    // modulus projection: lane holds a = 16 (2w + at) + lane%16 and
-    // n = 4 (lane/16) + r
+    // modulus projection: lane holds a = 16 w + lane%16 and n = 4 (lane/16) + r
     const float inv_ff = 1.0f / (float)FF;
 #pragma unroll
-    for (int at = 0; at < 2; ++at)
+    for (int r = 0; r < 4; ++r) {
+      float s = 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float s = 0.f;
+      for (int m = 0; m < kMfMaxModes; ++m)
+        if (m < M) s += ure[m][r] * ure[m][r] + uim[m][r] * uim[m][r];
+      const int a = 16 * wave + (lane & 15);
+      const int n = 4 * (lane >> 4) + r;
+      const float iv = fmaxf(I[a * F + n0 + n], 0.f);
+      const float g = (s > FLT_MIN) ? sqrtf(iv / s) * inv_ff : 0.f;
 #pragma unroll
-        for (int m = 0; m < kMfMaxModes; ++m)
-          if (m < M) s += ure[m][at][r] * ure[m][at][r] + uim[m][at][r] * uim[m][at][r];
-        const int a = 16 * (2 * wave + at) + (lane & 15);
-        const int n = 4 * (lane >> 4) + r;
-        const float iv = fmaxf(I[a * F + n0 + n], 0.f);
-        const float g = (s > FLT_MIN) ? sqrtf(iv / s) * inv_ff : 0.f;
-#pragma unroll
-        for (int m = 0; m < kMfMaxModes; ++m)
-          if (m < M) { ure[m][at][r] *= g; uim[m][at][r] *= g; }
-      }
+      for (int m = 0; m < kMfMaxModes; ++m)
+        if (m < M) { ure[m][r] *= g; uim[m][r] *= g; }
+    }
     // inverse column transform, one mode at a time through LDS
 #pragma unroll
     for (int m = 0; m < kMfMaxModes; ++m) {
       if (m < M) {
         __syncthreads();  // previous mode's fragments are consumed
         // element (n, a) of U'^T goes to A fragment ks = a/32, lane
-        // n + 16 ((a%32)/8), slot a%8; here a/32 = wave
+        // n + 16 ((a%32)/8), slot a%8; here a = 16 w + lane%16, so
+        // a/32 = w/2 and (a%32)/8 = 2 (w%2) + (lane%16)/8
 #pragma unroll
-        for (int at = 0; at < 2; ++at)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int n = 4 * (lane >> 4) + r;
-            const int l2 = n + 16 * (2 * at + ((lane & 15) >> 3));
-            const int slot = ((wave * 64 + l2) * 8) + (lane & 7);
-            const float vr = ure[m][at][r], vi = uim[m][at][r];
-            const uint32_t rh = mf_bf16_rne(vr), ih = mf_bf16_rne(vi);
-            const uint32_t rl = mf_bf16_rne(vr - __uint_as_float(rh << 16));
-            const uint32_t il = mf_bf16_rne(vi - __uint_as_float(ih << 16));
-            ua[0 * kMfKs * 512 + slot] = (uint16_t)rh;
-            ua[1 * kMfKs * 512 + slot] = (uint16_t)rl;
-            ua[2 * kMfKs * 512 + slot] = (uint16_t)ih;
-            ua[3 * kMfKs * 512 + slot] = (uint16_t)il;
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int n = 4 * (lane >> 4) + r;
+          const int l2 = n + 16 * (2 * (wave & 1) + ((lane & 15) >> 3));
+          const int slot = (((wave >> 1) * 64 + l2) * 8) + (lane & 7);
+          const float vr = ure[m][r], vi = uim[m][r];
+          const uint32_t rh = mf_bf16_rne(vr), ih = mf_bf16_rne(vi);
+          const uint32_t rl = mf_bf16_rne(vr - __uint_as_float(rh << 16));
+          const uint32_t il = mf_bf16_rne(vi - __uint_as_float(ih << 16));
+          ua[0 * kMfKs * 512 + slot] = (uint16_t)rh;
+          ua[1 * kMfKs * 512 + slot] = (uint16_t)rl;
+          ua[2 * kMfKs * 512 + slot] = (uint16_t)ih;
+          ua[3 * kMfKs * 512 + slot] = (uint16_t)il;
+        }
         __syncthreads();
         const uint4* uq = reinterpret_cast<const uint4*>(ua);
-        mf_f32x4 vre[2], vim[2];
-#pragma unroll
-        for (int at = 0; at < 2; ++at) {
-          vre[at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-          vim[at] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-        }
+        mf_f32x4 vre = mf_f32x4{0.f, 0.f, 0.f, 0.f}, vim = mf_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < kMfKs; ++ks) {
           MfA a;
@@ -318,24 +307,16 @@ __global__ __launch_bounds__(256) void k_mf_cols(const ScanDev* __restrict__ sca
           a.rl = uq[(1 * kMfKs + ks) * 64 + lane];
           a.ih = uq[(2 * kMfKs + ks) * 64 + lane];
           a.il = uq[(3 * kMfKs + ks) * 64 + lane];
-#pragma unroll
-          for (int at = 0; at < 2; ++at) {
-            const int nt = 2 * wave + at;
-            mf_cmma<true>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
-                          mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), vre[at],
-                          vim[at]);
-          }
+          mf_cmma<true>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
+                        mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), vre, vim);
         }
-        // V^T[n][a'] -> T[a'][n0 + n]; lane holds a' = 16 (2w + at) + lane%16,
+        // V^T[n][a'] -> T[a'][n0 + n]; lane holds a' = 16 w + lane%16,
         // n = 4 (lane/16) + r
         float2* __restrict__ Tm = T + (size_t)m * FF;
-#pragma unroll
-        for (int at = 0; at < 2; ++at) {
-          const int ap = 16 * (2 * wave + at) + (lane & 15);
-          float4* dst = reinterpret_cast<float4*>(Tm + ap * F + n0 + 4 * (lane >> 4));
-          dst[0] = make_float4(vre[at][0], vim[at][0], vre[at][1], vim[at][1]);
-          dst[1] = make_float4(vre[at][2], vim[at][2], vre[at][3], vim[at][3]);
-        }
+        const int ap = 16 * wave + (lane & 15);
+        float4* dst = reinterpret_cast<float4*>(Tm + ap * F + n0 + 4 * (lane >> 4));
+        dst[0] = make_float4(vre[0], vim[0], vre[1], vim[1]);
+        dst[1] = make_float4(vre[2], vim[2], vre[3], vim[3]);
       }
     }
     __syncthreads();  // the LDS fragments are rewritten by the next item

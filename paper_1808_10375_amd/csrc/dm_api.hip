@@ -627,14 +627,16 @@ int mfma_grid(dm_ctx* c, int items) {
 
 dm_status launch_views_mfma(dm_ctx* c) {
   const int M = c->M, nv = c->total_views;
-  hipLaunchKernelGGL(dmk::k_mf_rows_fwd, dim3(mfma_grid(c, nv * M)), dim3(256), kMfLdsW,
+  hipLaunchKernelGGL(dmk::k_mf_rows_fwd, dim3(mfma_grid(c, nv * M)),
+                     dim3(dmk::kMfRowsThreads), kMfLdsW,
                      c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
   DM_LAUNCHED(c, "k_mf_rows_fwd");
   hipLaunchKernelGGL(dmk::k_mf_cols, dim3(mfma_grid(c, nv * dmk::kMfNt)),
                      dim3(dmk::kMfColsThreads), kMfLdsCols,
                      c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
   DM_LAUNCHED(c, "k_mf_cols");
-  hipLaunchKernelGGL(dmk::k_mf_rows_inv, dim3(mfma_grid(c, nv * 2)), dim3(256), kMfLdsW,
+  hipLaunchKernelGGL(dmk::k_mf_rows_inv, dim3(mfma_grid(c, nv)), dim3(dmk::kMfRowsThreads),
+                     kMfLdsW,
                      c->stream, c->scan_dev(), c->vmap(), nv, M, c->wf());
   DM_LAUNCHED(c, "k_mf_rows_inv");
   return DM_OK;

@@ -122,12 +122,15 @@ __device__ __forceinline__ void mf_load_w(uint4* wl, const uint4* __restrict__ w
 
 // ---------------------------------------------------------------------------
 // (1) row transform: T[r][c] = sum_k Z[r][k] W[k][c] for one (view, mode)
-// frame per iteration of the block loop; wave w owns rows 32w .. 32w+31.
+// frame per iteration of the block loop; eight waves (two per SIMD), wave w
+// owns rows 16w .. 16w+15.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mf_rows_fwd(const ScanDev* __restrict__ scans,
-                                                     const int2* __restrict__ vmap,
-                                                     int total_views, int M,
-                                                     const uint4* __restrict__ wf) {
+constexpr int kMfRowsThreads = 512;
+
+__global__ __launch_bounds__(kMfRowsThreads) void k_mf_rows_fwd(const ScanDev* __restrict__ scans,
+                                                                const int2* __restrict__ vmap,
+                                                                int total_views, int M,
+                                                                const uint4* __restrict__ wf) {
   extern __shared__ uint4 wl[];
   mf_load_w(wl, wf);
   constexpr int F = kMfF, FF = F * F;
@@ -144,65 +147,50 @@ __global__ __launch_bounds__(256) void k_mf_rows_fwd(const ScanDev* __restrict__
     const float2* __restrict__ P = sc.P + (size_t)m * FF;
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
     float2* __restrict__ T = sc.tspec + ((size_t)j * M + m) * FF;
-    mf_f32x4 re[2][kMfNt], im[2][kMfNt];
+    mf_f32x4 re[kMfNt], im[kMfNt];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int nt = 0; nt < kMfNt; ++nt) {
-        re[rt][nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-        im[rt][nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
-      }
+    for (int nt = 0; nt < kMfNt; ++nt) {
+      re[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
+      im[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int row = 16 * wave + (lane & 15);
     // the raw loads of k step ks + 1 go out before the products of step ks
-    float2 pv[2][8], ov[2][8], sv[2][8];
+    float2 pv[8], ov[8], sv[8];
     auto load_step = [&](int ks) {
+      const int k0 = 32 * ks + 8 * (lane >> 4);
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const int row = 32 * wave + 16 * rt + (lane & 15);
-        const int k0 = 32 * ks + 8 * (lane >> 4);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          pv[rt][e] = P[row * F + k0 + e];
-          ov[rt][e] = O[(size_t)row * W + k0 + e];
-          sv[rt][e] = psi[row * F + k0 + e];
-        }
+      for (int e = 0; e < 8; ++e) {
+        pv[e] = P[row * F + k0 + e];
+        ov[e] = O[(size_t)row * W + k0 + e];
+        sv[e] = psi[row * F + k0 + e];
       }
     };
     load_step(0);
 #pragma unroll
     for (int ks = 0; ks < kMfKs; ++ks) {
-      MfA a[2];
+      float2 z[8];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        float2 z[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float2 phi = cmul(pv[rt][e], ov[rt][e]);
-          z[e] = make_float2(2.f * phi.x - sv[rt][e].x, 2.f * phi.y - sv[rt][e].y);
-        }
-        a[rt] = mf_split_complex(z);
+      for (int e = 0; e < 8; ++e) {
+        const float2 phi = cmul(pv[e], ov[e]);
+        z[e] = make_float2(2.f * phi.x - sv[e].x, 2.f * phi.y - sv[e].y);
       }
+      const MfA a = mf_split_complex(z);
       if (ks + 1 < kMfKs) {
         load_step(ks + 1);
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int nt = 0; nt < kMfNt; ++nt) {
-        const uint4 wrh = mf_w(wl, 0, ks, nt, lane), wrl = mf_w(wl, 1, ks, nt, lane);
-        const uint4 wih = mf_w(wl, 2, ks, nt, lane), wil = mf_w(wl, 3, ks, nt, lane);
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-          mf_cmma<false>(a[rt], wrh, wrl, wih, wil, re[rt][nt], im[rt][nt]);
-      }
+      for (int nt = 0; nt < kMfNt; ++nt)
+        mf_cmma<false>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
+                       mf_w(wl, 2, ks, nt, lane), mf_w(wl, 3, ks, nt, lane), re[nt], im[nt]);
     }
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int nt = 0; nt < kMfNt; ++nt)
 #pragma unroll
-      for (int nt = 0; nt < kMfNt; ++nt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 32 * wave + 16 * rt + 4 * (lane >> 4) + r;
-          T[row * F + 16 * nt + (lane & 15)] = make_float2(re[rt][nt][r], im[rt][nt][r]);
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int orow = 16 * wave + 4 * (lane >> 4) + r;
+        T[orow * F + 16 * nt + (lane & 15)] = make_float2(re[nt][r], im[nt][r]);
+      }
   }
 }
 
@@ -324,29 +312,29 @@ __global__ __launch_bounds__(kMfColsThreads) void k_mf_cols(const ScanDev* __res
 }
 
 // ---------------------------------------------------------------------------
-// (3) inverse row transform and the view update for 64 rows (half h) of all
-// modes of one view; wave w owns rows 64h + 16w .. +15.
+// (3) inverse row transform and the view update for all rows and modes of
+// one view; eight waves (two per SIMD), wave w owns rows 16w .. 16w+15.  The
+// view's eps_psi partials go to part 2j (part 2j + 1 is left at zero).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__ scans,
+__global__ __launch_bounds__(kMfRowsThreads) void k_mf_rows_inv(const ScanDev* __restrict__ scans,
                                                      const int2* __restrict__ vmap,
                                                      int total_views, int M,
                                                      const uint4* __restrict__ wf) {
   extern __shared__ uint4 wl[];
   mf_load_w(wl, wf);
-  __shared__ float red[8];
+  __shared__ float red[2 * (kMfRowsThreads / 64)];
   constexpr int F = kMfF, FF = F * F;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int total = total_views * 2;
+  const int total = total_views;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int2 vm = vmap[item >> 1];
-    const int h = item & 1;
+    const int2 vm = vmap[item];
     const ScanDev& sc = scans[vm.x];
     const int j = uni(vm.y);
     const int W = uni(sc.W);
     const float beta = sc.beta;
     const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
-    const int rbase = 64 * h + 16 * wave;
+    const int rbase = 16 * wave;
     float2 oacc[kMfNt][4];
 #pragma unroll
     for (int nt = 0; nt < kMfNt; ++nt)
@@ -363,16 +351,11 @@ __global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__
         re[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
         im[nt] = mf_f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      // all of this mode's row loads first: one memory latency per mode
-      float2 zall[kMfKs][8];
-#pragma unroll
-      for (int ks = 0; ks < kMfKs; ++ks)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          zall[ks][e] = V[(rbase + (lane & 15)) * F + 32 * ks + 8 * (lane >> 4) + e];
-#pragma unroll
       for (int ks = 0; ks < kMfKs; ++ks) {
-        const MfA a = mf_split_complex(zall[ks]);
+        float2 z[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[e] = V[(rbase + (lane & 15)) * F + 32 * ks + 8 * (lane >> 4) + e];
+        const MfA a = mf_split_complex(z);
 #pragma unroll
         for (int nt = 0; nt < kMfNt; ++nt)
           mf_cmma<true>(a, mf_w(wl, 0, ks, nt, lane), mf_w(wl, 1, ks, nt, lane),
@@ -410,10 +393,12 @@ __global__ __launch_bounds__(256) void k_mf_rows_inv(const ScanDev* __restrict__
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         oj[(rbase + 4 * (lane >> 4) + r) * F + 16 * nt + (lane & 15)] = oacc[nt][r];
-    block_sum2<256>(e_d, e_n, red);
+    block_sum2<kMfRowsThreads>(e_d, e_n, red);
     if (threadIdx.x == 0) {
-      sc.err_psi[2 * (2 * j + h)] = e_d;
-      sc.err_psi[2 * (2 * j + h) + 1] = e_n;
+      sc.err_psi[4 * j] = e_d;
+      sc.err_psi[4 * j + 1] = e_n;
+      sc.err_psi[4 * j + 2] = 0.f;
+      sc.err_psi[4 * j + 3] = 0.f;
     }
     __syncthreads();  // red is reused by the next item
   }

@@ -7,7 +7,7 @@
  * view's diffraction frame it predicts the object patch under that view's
  * window; the patches are stitched into an initial object with the Eq. 5
  * weights (dm_warm_start in dm.h).  Plain DM from the cold start remains the
- * fallback and the judge of the result.
+ * fallback and the reference the warm start is measured against.
  *
  * Network (U-Net style encoder-decoder, NCHW float32 activations):
  *   input   [n][1][S][S]: log1p of 2x2-binned intensities / 10 (see

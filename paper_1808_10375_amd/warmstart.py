@@ -6,7 +6,7 @@ results (Section III).  Here the pre-existing results are DM reconstructions
 of synthetic scans: a network learns to map one diffraction frame to the
 object under its window, and its patches, stitched with the object update
 of Eq. 5, replace the flat initial object.  Plain DM from the flat object
-stays the fallback and the judge.
+stays the fallback and the reference the warm start is measured against.
 
 Every arithmetic step of the reconstruction and of the network runs in
 libdm's kernels (dm.py, dmnet.py).  Host code here only prepares training

@@ -1030,7 +1030,10 @@ dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
   DM_TRY(apply_tuning(c, t));
   const uint32_t saved_flags = c->flags;
   c->flags &= ~DM_FLAG_PHASE_TIMING;
-  dm_status s = launch_iteration(c, false);  // warm-up
+  // time the form the context's iterations run (with the eps_psi partials
+  // unless DM_FLAG_PSI_ERROR_LAST)
+  const bool psi_err = !(c->flags & DM_FLAG_PSI_ERROR_LAST);
+  dm_status s = launch_iteration(c, psi_err);  // warm-up
   std::vector<double> v;
   for (int r = 0; r < reps && s == DM_OK; ++r) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -1038,7 +1041,7 @@ dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
     if (e == hipSuccess) e = take_event(c, &b);
     if (e == hipSuccess) e = hipEventRecord(a, c->stream);
     if (e != hipSuccess) { s = fail_hip(c, e, "autotune events"); break; }
-    s = launch_iteration(c, false);
+    s = launch_iteration(c, psi_err);
     if (s != DM_OK) break;
     e = hipEventRecord(b, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(b);

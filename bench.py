@@ -277,8 +277,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the frame-sharded "
-                          "multi-GPU form is a design, not built (use --gpus 1)"}))
+        print(json.dumps({"error": "the library runs on one GPU: the view-sharded "
+                          "multi-GPU form is designed, not built (use --gpus 1)"}))
         sys.exit(2)
 
     import torch

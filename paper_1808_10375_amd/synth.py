@@ -12,7 +12,7 @@ P_m * O_window_j (Section II, Eqs. 1-2 of the paper).  The transform here is
 numpy's unnormalised forward FFT with exp(-2*pi*i*k*n/F), detector DC at [0,0]
 (no fftshift); the reconstruction must use the same convention.
 
-Workload shapes follow the paper's cases as restated for this project:
+Workload shapes follow the paper's cases, restated as synthetic scans:
   single_mode_raster_32   single mode, 32x32 frames, 10x10 jittered raster, 128x128 object,
             noise-free
   multimode_spiral_128    5 Hermite-Gaussian modes, 128x128 frames, 2500-point Fermat spiral,

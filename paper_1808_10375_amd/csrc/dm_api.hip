@@ -560,7 +560,7 @@ dm_status launch_views_multipass(dm_ctx* c) {
 // BF16x3 form: three persistent kernels, one block per CU, each holding the
 // split DFT matrix in LDS
 constexpr size_t kMfLdsW = sizeof(uint4) * dmk::kMfWords;
-constexpr size_t kMfLdsCols = kMfLdsW + 4 * dmk::kMfKs * 64 * 16;
+constexpr size_t kMfLdsCols = kMfLdsW + 2 * 4 * dmk::kMfKs * 64 * 16;  // 160 KB
 
 hipError_t set_mfma_lds() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dmk::k_mf_rows_fwd),

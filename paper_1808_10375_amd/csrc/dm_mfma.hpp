@@ -212,8 +212,11 @@ __global__ __launch_bounds__(kMfColsThreads) void k_mf_cols(const ScanDev* __res
   extern __shared__ uint4 wl[];
   mf_load_w(wl, wf);
   // U' of one mode in A-fragment order: [mat][ks][lane] uint4, mat = re hi,
-  // re lo, im hi, im lo
-  uint16_t* ua = reinterpret_cast<uint16_t*>(wl + kMfWords);
+  // re lo, im hi, im lo; two buffers, used by alternate modes, so that one
+  // barrier per mode suffices (a wave writes mode m + 1's fragments only
+  // after every wave has passed mode m's barrier, i.e. finished reading the
+  // buffer of mode m - 1)
+  uint16_t* const ua2 = reinterpret_cast<uint16_t*>(wl + kMfWords);
   constexpr int F = kMfF, FF = F * F;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nt = wave;  // this wave's 16 columns of the transform output
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(kMfColsThreads) void k_mf_cols(const ScanDev* __res
 #pragma unroll
     for (int m = 0; m < kMfMaxModes; ++m) {
       if (m < M) {
-        __syncthreads();  // previous mode's fragments are consumed
+        uint16_t* const ua = ua2 + (m & 1) * (4 * kMfKs * 512);
         // element (n, a) of U'^T goes to A fragment ks = a/32, lane
         // n + 16 ((a%32)/8), slot a%8; here a = 16 w + lane%16, so
         // a/32 = w/2 and (a%32)/8 = 2 (w%2) + (lane%16)/8

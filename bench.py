@@ -252,6 +252,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--paper-frame", action="store_true",
+                    help="the fly scan at the paper's own frame size instead: 10000 views x "
+                         "4 modes x 188^2 frames (mixed-radix transforms)")
     ap.add_argument("--conv-iters", type=int, default=100,
                     help="total iterations from the cold start for the err curve")
     ap.add_argument("--cpu-sample", type=int, default=300)
@@ -290,7 +293,12 @@ def main():
     dev = torch.device("cuda:0")
 
     t0 = time.time()
-    if args.config == 1:
+    if args.paper_frame:
+        scan = synth.flyscan_raster_188(3)
+        workload = ("fly scan at the paper's frame size: 10000 views x 4 modes, 188x188 frames, "
+                    "100x100 raster, 1280x1280 object, 8-position motion blur, "
+                    "Poisson 1e6 photons/frame")
+    elif args.config == 1:
         scan = synth.multimode_spiral_128(1)
         workload = ("multi-mode spiral: 2500 views x 5 Hermite-Gaussian modes, 128x128 frames, "
                     "Fermat spiral (10 px step), 1024x1024 object, Poisson 1e5 photons/frame")
@@ -371,6 +379,13 @@ def main():
         "iters_to_err_1e-3": reach,
         "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
     }
+    if args.paper_frame:
+        # context only: the paper's measured rate on its 10000-frame 188^2
+        # scan (FP64, four V100s, 50 iterations in 25.69 s; mode count not
+        # stated), in views per second
+        out["views_per_s"] = n / (elapsed / args.steps)
+        out["paper_context"] = {"views_per_s": 10000 * 50 / 25.69,
+                                "hardware": "4x V100, FP64", "comparable": False}
     if args.precision == "bf16x3":
         flops = 96.0 * f ** 3 * n * m
         out["roofline"] = {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
@@ -379,7 +394,8 @@ def main():
                            "traffic": None, "kernel": "views (3 MFMA kernels)",
                            "alg_flops_per_launch": flops, "avg_launch_ms": views_ms}
         out["dtype"] = "bf16x3/f32"
-    if not args.no_forms and args.config == 1 and args.precision == "fp32":
+    if (not args.no_forms and args.config == 1 and not args.paper_frame
+            and args.precision == "fp32"):
         out["forms"] = {"psi_error_last": bench_psi_error_last(scan, args.steps, args.warmup),
                         "batched": bench_batched(args.steps, args.warmup, args.conv_iters),
                         "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,

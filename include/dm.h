@@ -87,7 +87,8 @@ typedef enum {
 
 /* dm_desc.flags bits */
 #define DM_FLAG_MULTIPASS 1u     /* use the three-kernel transform path for any
-                                    F (it is always used for F = 256)       */
+                                    F (it is always used for F = 256, 188
+                                    and 200)                                */
 #define DM_FLAG_PHASE_TIMING 2u  /* bracket every phase launch of
                                     dm_iterate with HIP events on the
                                     context's stream (read by
@@ -121,7 +122,11 @@ typedef enum {
 
 typedef struct {
   int32_t n_frames;   /* N >= 1                                          */
-  int32_t frame;      /* F: power of two, 16 <= F <= 256                 */
+  int32_t frame;      /* F: power of two, 16 <= F <= 256, or 188 or 200
+                         (the paper's frame sizes: 4 x 47, 8 x 25; these
+                         run the three-kernel path with mixed-radix line
+                         transforms and take extra workspace for the
+                         spectrum buffer, N M F^2 complex values)        */
   int32_t n_modes;    /* M: 1 <= M <= 16 probe modes                     */
   int32_t obj_h;      /* H >= F                                          */
   int32_t obj_w;      /* W >= F                                          */
@@ -165,8 +170,8 @@ typedef struct {
   int32_t view_path;     /* transform path of the view update (Eq. 3):
                             DM_VIEWS_FUSED, DM_VIEWS_THREE_KERNEL (only
                             where the workspace holds its spectrum buffer:
-                            F = 256 or DM_FLAG_MULTIPASS at init; forced for
-                            F = 256), or one of the DM_VIEWS_STREAMED*
+                            F = 256, 188, 200 or DM_FLAG_MULTIPASS at init;
+                            forced for F = 256, 188 and 200), or one of the DM_VIEWS_STREAMED*
                             paths (F <= 128); ignored by
                             the BF16x3 form, which must be given 0        */
   int32_t reserved;      /* must be 0                                     */

@@ -16,6 +16,7 @@
 #include "../../include/dm.h"
 #include "dm_kernels.hpp"
 #include "dm_mfma.hpp"
+#include "dm_mixed.hpp"
 
 using dmk::DevErrors;
 using dmk::ScanDev;
@@ -30,6 +31,8 @@ constexpr size_t kAlign = 256;
 constexpr int kObjGroups = 4;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+// frame edges that are not powers of two: F = R * Q (dm_mixed.hpp)
+bool is_mixed(int F) { return F == 188 || F == 200; }
 
 // ---------------------------------------------------------------------------
 // launch shapes
@@ -44,7 +47,7 @@ int default_chunks(int F) {
 bool is_bf16x3(const dm_desc& d) { return d.precision == DM_BF16X3_DFT; }
 
 bool has_spectrum_buffer(const dm_desc& d) {
-  return d.frame == 256 || (d.flags & DM_FLAG_MULTIPASS) || is_bf16x3(d);
+  return d.frame == 256 || is_mixed(d.frame) || (d.flags & DM_FLAG_MULTIPASS) || is_bf16x3(d);
 }
 
 dm_tuning default_tuning(const dm_desc& d) {
@@ -81,6 +84,34 @@ int row_block(int F) {
   return std::min(256 / B, F);
 }
 
+// row blocks per frame of the three-kernel path (one eps_psi partial each)
+int row_parts(int F) {
+  switch (F) {
+    case 188: return dmk::MixRows<188>::NBLK;
+    case 200: return dmk::MixRows<200>::NBLK;
+  }
+  return F / row_block(F);
+}
+
+int mix_q(int F) { return F == 188 ? dmk::MixCfg<188>::Q : dmk::MixCfg<200>::Q; }
+
+// columns per block of the mixed-radix column kernel: a power of two up to
+// 16 with CB * M * Q threads (rounded to whole waves) at most 1024
+int mix_cols_per_block(int F, int M) {
+  const int Q = mix_q(F);
+  int p = 1;
+  while (p * 2 <= 16 && ((p * 2 * M * Q + 63) / 64) * 64 <= 1024) p *= 2;
+  return p;
+}
+
+int mix_cols_threads(int F, int M, int cb) { return ((cb * M * mix_q(F) + 63) / 64) * 64; }
+
+// dynamic LDS of the mixed-radix column kernel: cb * M exchange lines of
+// Q * R + 2 complex values, the mode powers [M][cb][F] and the scale [cb][F]
+size_t mix_cols_lds_bytes(int F, int M, int cb) {
+  return (size_t)cb * M * (F + 2) * sizeof(float2) + (size_t)(M + 1) * cb * F * sizeof(float);
+}
+
 // ---------------------------------------------------------------------------
 // workspace carving: a context header, then one region per scan
 // ---------------------------------------------------------------------------
@@ -106,7 +137,7 @@ ScanLayout scan_layout(const dm_desc& d) {
   L.ntiles16 = tiles_for(d.obj_h, d.obj_w, 16);  // the larger of the two tile counts
   L.nnz16 = std::max(nnz_bound(d, 16), nnz_bound(d, 32));
   L.n_psi_parts_fused = (int)N;
-  L.n_psi_parts_multi = (int)N * ((int)F / row_block((int)F));
+  L.n_psi_parts_multi = (int)N * row_parts((int)F);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -194,8 +225,8 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
   if (d->n_frames < 1) { why = "n_frames must be >= 1"; return DM_E_ARG; }
   if (d->n_modes < 1) { why = "n_modes must be >= 1"; return DM_E_ARG; }
   if (d->n_modes > DM_MAX_MODES) { why = "n_modes > 16 not supported"; return DM_E_UNSUPPORTED; }
-  if (!is_pow2(d->frame) || d->frame < 16 || d->frame > 256) {
-    why = "frame must be a power of two in [16, 256]";
+  if (!(is_pow2(d->frame) && d->frame >= 16 && d->frame <= 256) && !is_mixed(d->frame)) {
+    why = "frame must be a power of two in [16, 256], 188 or 200";
     return DM_E_UNSUPPORTED;
   }
   if (d->obj_h < d->frame || d->obj_w < d->frame) { why = "object smaller than a frame"; return DM_E_ARG; }
@@ -485,7 +516,12 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
                            hipMemcpyHostToDevice, c->stream));
   DM_HIP(c, hipMemcpyAsync(c->cmap(), cmap.data(), cmap.size() * sizeof(int2),
                            hipMemcpyHostToDevice, c->stream));
-  if (t.view_path == DM_VIEWS_THREE_KERNEL) {
+  if (t.view_path == DM_VIEWS_THREE_KERNEL && is_mixed(c->F)) {
+    const int lds = (int)mix_cols_lds_bytes(c->F, c->M, mix_cols_per_block(c->F, c->M));
+    const void* k = c->F == 188 ? reinterpret_cast<const void*>(dmk::k_mix_cols<188>)
+                                : reinterpret_cast<const void*>(dmk::k_mix_cols<200>);
+    DM_HIP(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  } else if (t.view_path == DM_VIEWS_THREE_KERNEL) {
     const int lds =
         (int)cols_lds_bytes(c->F, c->M, cols_per_block(c->F, c->M));
     DM_HIP(c, set_cols_lds(c->F, lds));
@@ -554,6 +590,26 @@ dm_status launch_views_multipass(dm_ctx* c) {
   hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,
                      c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_rows_inv");
+  return DM_OK;
+}
+
+// Frames of edge F = R * Q (188, 200): the same three passes with the
+// mixed-radix line transforms.
+template <int F>
+dm_status launch_views_mixed(dm_ctx* c) {
+  using C = dmk::MixRows<F>;
+  const int M = c->M;
+  hipLaunchKernelGGL(dmk::k_mix_rows_fwd<F>, dim3(c->total_views * M, C::NBLK), dim3(C::NT), 0,
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  DM_LAUNCHED(c, "k_mix_rows_fwd");
+  const int cb = mix_cols_per_block(F, M);
+  hipLaunchKernelGGL(dmk::k_mix_cols<F>, dim3(c->total_views * ((F + cb - 1) / cb)),
+                     dim3(mix_cols_threads(F, M, cb)), mix_cols_lds_bytes(F, M, cb), c->stream,
+                     c->scan_dev(), c->vmap(), c->tw(), M, cb);
+  DM_LAUNCHED(c, "k_mix_cols");
+  hipLaunchKernelGGL(dmk::k_mix_rows_inv<F>, dim3(c->total_views, C::NBLK), dim3(C::NT), 0,
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  DM_LAUNCHED(c, "k_mix_rows_inv");
   return DM_OK;
 }
 
@@ -702,6 +758,8 @@ dm_status launch_views(dm_ctx* c, bool psi_err, bool* psi_valid) {
       case 64: return launch_views_multipass<64>(c);
       case 128: return launch_views_multipass<128>(c);
       case 256: return launch_views_multipass<256>(c);
+      case 188: return launch_views_mixed<188>(c);
+      case 200: return launch_views_mixed<200>(c);
     }
   }
   c->err = "unsupported frame size for this transform path";
@@ -1019,7 +1077,7 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     return DM_E_ARG;
   }
   if (t.view_path != DM_VIEWS_THREE_KERNEL && c->F > 128) {
-    c->err = "F = 256 only has the three-kernel path";
+    c->err = "frames above 128 only have the three-kernel path";
     return DM_E_ARG;
   }
   return DM_OK;

@@ -1204,6 +1204,7 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
   float2* __restrict__ num_part = sc.num_part;
   float* __restrict__ den_part = sc.den_part;
   const int N = sc.N, W = sc.W, chunk = sc.chunk;
+  if (pix >= FF) return;  // F * F need not fill the last block (no barriers here)
   const int j0 = cidx * chunk;
   const int j1 = min(N, j0 + chunk);
   const int u = pix / F, v = pix % F;
@@ -1264,7 +1265,10 @@ __global__ __launch_bounds__(256) void k_probe_final(const ScanDev* __restrict__
   float* __restrict__ D = sc.D;
   float* __restrict__ err_probe = sc.err_probe;
   const int C = sc.C;
-  const int pix = blockIdx.x * 256 + threadIdx.x;
+  // pixels past F * F (frames whose F * F is not a multiple of 256) read
+  // pixel 0 and store nothing; they stay for the block sums' barriers
+  const bool in = blockIdx.x * 256 + threadIdx.x < FF;
+  const int pix = in ? blockIdx.x * 256 + threadIdx.x : 0;
   // chunk partials are added in chunk order; loads go out in batches of 8
   float den = 0.f;
   int cc = 0;
@@ -1294,8 +1298,8 @@ __global__ __launch_bounds__(256) void k_probe_final(const ScanDev* __restrict__
       const float inv = 1.0f / den;
       pn = make_float2(num.x * inv, num.y * inv);
     }
-    P[(size_t)m * FF + pix] = pn;
-    float e_d = cabs2(csub(pn, po)), e_n = cabs2(pn);
+    if (in) P[(size_t)m * FF + pix] = pn;
+    float e_d = in ? cabs2(csub(pn, po)) : 0.f, e_n = in ? cabs2(pn) : 0.f;
     dsum += e_n;
     block_sum2<256>(e_d, e_n, red);
     if (threadIdx.x == 0) {
@@ -1303,7 +1307,7 @@ __global__ __launch_bounds__(256) void k_probe_final(const ScanDev* __restrict__
       err_probe[((size_t)blockIdx.x * M + m) * 2 + 1] = e_n;
     }
   }
-  D[pix] = dsum;
+  if (in) D[pix] = dsum;
 }
 
 // ---------------------------------------------------------------------------

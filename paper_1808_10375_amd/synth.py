@@ -21,6 +21,8 @@ Workload shapes follow the paper's cases, restated as synthetic scans:
             sub-positions of motion blur, Poisson noise at 1e6 photons/frame,
             reconstructed with 8 modes (Section II: fly-scan blur read as
             incoherent illumination)
+  flyscan_raster_188      the paper's frame size: 188x188 frames, 100x100 raster, 1280x1280
+            object, 8 sub-positions of motion blur, 1e6 photons/frame, 4 modes
   uneven_spirals_128      16 scans of 200-3000 frames, 3 modes, 128x128 frames, 1024^2 objects
 The paper measured real beamline data that is not available; these seeded
 scans stand in for it.
@@ -343,6 +345,34 @@ def flyscan_raster_256(seed: int = 2, n_frames: int = 10000, n_modes: int = 8,
                         r[3], env, weights, (obj, obj))
     return Scan(I, pos, P0, O0, 0.8, probes.astype(np.complex64),
                 O.astype(np.complex64), "flyscan_raster_256")
+
+
+def flyscan_raster_188(seed: int = 3, n_frames: int = 10000, n_modes: int = 4,
+                       obj: int = 1280, sub_positions: int = 8) -> Scan:
+    """Fly scan at the paper's own frame size (188 = 4 x 47; its measured
+    gold nano-crystal scan has 10000 such frames): 188x188 frames on a
+    100x100 raster (step 9 px, origin 100 px), 1280x1280 object, HG00 source
+    probe (waist 23.5 px = F/8, quadratic phase pi/94^2), motion blur from
+    `sub_positions` sub-positions along x at offsets (s - 3.5) * 1.1 px summed
+    incoherently, 1e6 photons/frame, reconstructed with `n_modes` modes.
+    `n_frames` < 10000 takes the first rows of the raster."""
+    r = streams(seed)
+    f = 188
+    O = grf_object(obj, obj, r[0], r[1])
+    src = hermite_gauss_modes(f, f / 8.0, [(0, 0)], [1.0])[0]
+    full = raster_positions(100, 100, 9.0, 100.0)
+    pos = full[:n_frames]
+    shifts = [(s - (sub_positions - 1) / 2.0) * 1.1 for s in range(sub_positions)]
+    probes = np.stack([subpixel_shift(src, 0.0, dx) for dx in shifts])
+    I_exact = far_field_intensity(probes, O, pos, chunk=64)
+    I, _ = poisson_counts(I_exact, 1e6, r[2])
+    y, x = _centred_grid(f)
+    env = np.exp(-(x * x + y * y) / (f / 8.0) ** 2)
+    weights = [1.0 / (k + 1) for k in range(n_modes)]
+    P0, O0 = cold_start(f, n_modes, float(np.mean(np.sum(I, axis=(1, 2)))),
+                        r[3], env, weights, (obj, obj))
+    return Scan(I, pos, P0, O0, 0.8, probes.astype(np.complex64),
+                O.astype(np.complex64), "flyscan_raster_188")
 
 
 def uneven_scan_sizes(seed: int = 1000, n_scans: int = 16, lo: int = 200,

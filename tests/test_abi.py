@@ -55,6 +55,13 @@ def test_workspace_bytes_valid_and_invalid():
                 dict(n_modes=17), dict(beta=1.5), dict(beta=-0.1), dict(obj_h=16),
                 dict(n_frames=0), dict(precision=7), dict(flags=16), dict(flags=6)):
         assert dm.dm_workspace_bytes(desc(**bad)) == 0, bad
+    # the paper's frame edges 188 and 200 run the three-kernel path: psi
+    # and the spectrum buffer
+    for f in (188, 200):
+        assert dm.dm_workspace_bytes(desc(frame=f, obj_h=300, obj_w=300)) > \
+            2 * 10 * 2 * f * f * 8, f
+    for bad in (dict(frame=189), dict(frame=100), dict(frame=200, precision=dm.DM_BF16X3_DFT)):
+        assert dm.dm_workspace_bytes(desc(obj_h=300, obj_w=300, **bad)) == 0, bad
     # F = 256 needs the multi-pass spectrum buffer as well
     d256 = desc(frame=256, obj_h=300, obj_w=300)
     assert dm.dm_workspace_bytes(d256) > 2 * 10 * 2 * 256 * 256 * 8

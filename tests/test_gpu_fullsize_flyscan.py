@@ -1,7 +1,8 @@
-"""The fly scan at its full size: 10000 views x 8 modes x 256^2 frames,
-3072^2 object (psi alone is 41.9 GB), one iteration from the initial views
-in the launch configuration the benchmark times (the library's default
-tuning for the context).
+"""The fly scans at full size, one iteration from the initial views in the
+launch configuration the benchmark times (the library's default tuning for
+the context): 10000 views x 8 modes x 256^2 frames on a 3072^2 object (psi
+alone is 41.9 GB), and the paper's frame size, 10000 views x 4 modes x
+188^2 frames on a 1280^2 object (mixed-radix transforms).
 
 The whole FP64 iteration is too slow for a test, so the oracle is applied
 where it can be computed one piece at a time:
@@ -38,12 +39,24 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def test_flyscan_10000x8_256_full_size_sampled():
+CASES = {
+    256: dict(make=lambda: synth.flyscan_raster_256(2), shape=(10000, 8, 256, 3072),
+              obj_px=[(1500, 1500), (1000, 1800), (2000, 1100), (1234, 1777), (1900, 1950)],
+              probe_px=[(128, 128), (120, 140), (100, 128), (128, 160), (150, 110)]),
+    188: dict(make=lambda: synth.flyscan_raster_188(3), shape=(10000, 4, 188, 1280),
+              obj_px=[(640, 640), (400, 800), (900, 300), (1000, 1000), (733, 457)],
+              probe_px=[(94, 94), (80, 100), (60, 94), (94, 120), (110, 70)]),
+}
+
+
+@pytest.mark.parametrize("frame", [256, 188])
+def test_flyscan_10000_views_full_size_sampled(frame):
     from paper_1808_10375_amd import dm
-    say("case fly scan full size: 10000 views x 8 modes x 256^2, 3072^2 object")
-    s = synth.flyscan_raster_256(2)
-    n, m, f = s.n_frames, s.n_modes, s.frame
-    assert (n, m, f) == (10000, 8, 256) and s.obj_shape == (3072, 3072)
+    cfg = CASES[frame]
+    n, m, f, o = cfg["shape"]
+    say(f"case fly scan full size: {n} views x {m} modes x {f}^2, {o}^2 object")
+    s = cfg["make"]()
+    assert (s.n_frames, s.n_modes, s.frame) == (n, m, f) and s.obj_shape == (o, o)
     dev = torch.device("cuda:0")
     ctx = dm.DMContext(torch.from_numpy(s.I).to(dev), s.pos, torch.from_numpy(s.P0).to(dev),
                        torch.from_numpy(s.O0).to(dev), beta=s.beta)
@@ -69,7 +82,7 @@ def test_flyscan_10000x8_256_full_size_sampled():
     # O' at sampled object pixels (Eq. 5 from the GPU's psi' and P0)
     O_g = O_t.cpu().numpy()
     worst = 0.0
-    for (y, x) in [(1500, 1500), (1000, 1800), (2000, 1100), (1234, 1777), (1900, 1950)]:
+    for (y, x) in cfg["obj_px"]:
         jj = np.nonzero((pos[:, 0] <= y) & (y < pos[:, 0] + f) &
                         (pos[:, 1] <= x) & (x < pos[:, 1] + f))[0]
         u, v = y - pos[jj, 0], x - pos[jj, 1]
@@ -89,7 +102,7 @@ def test_flyscan_10000x8_256_full_size_sampled():
     # P' at sampled probe pixels (Eq. 4 over all views, GPU psi' and new O)
     P_g = P_t.cpu().numpy()
     worst = 0.0
-    for (u, v) in [(128, 128), (120, 140), (100, 128), (128, 160), (150, 110)]:
+    for (u, v) in cfg["probe_px"]:
         o = O_t[torch.as_tensor(pos[:, 0] + u, device=dev),
                 torch.as_tensor(pos[:, 1] + v, device=dev)].cpu().numpy().astype(np.complex128)
         vals = psi_t[:, :, u, v].cpu().numpy().astype(np.complex128)   # [views][modes]

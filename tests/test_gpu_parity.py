@@ -276,6 +276,59 @@ def test_flyscan_256_strip_one_step():
     one_step_case(dict(psi=psi0, P=s.P0, O=s.O0, I=s.I, pos=s.pos, beta=0.8))
 
 
+MIXED = [
+    # (seed, N, F, M, H, W, perturb): the paper's frame edges 188 = 4 x 47 and
+    # 200 = 8 x 25.  One mode: 16-column blocks, the last one partial; F =
+    # 188: five-row blocks, the last one with three rows; 16 modes: one or two
+    # columns per block.  Many random modes on few views make the probe
+    # division ill-conditioned, so those cases start near a physical state.
+    (51, 9, 188, 1, 300, 260, None),
+    (52, 7, 188, 4, 260, 300, None),
+    (53, 6, 200, 3, 280, 320, None),
+    (54, 11, 200, 8, 300, 300, 0.5),
+    (55, 5, 188, 16, 230, 200, 0.5),
+    (56, 5, 200, 16, 210, 240, 0.5),
+]
+
+
+@pytest.mark.parametrize("seed,n,f,m,h,w,perturb", MIXED)
+def test_one_step_mixed_radix_frames(seed, n, f, m, h, w, perturb):
+    say(f"case mixed radix seed={seed} N={n} F={f} M={m} obj={h}x{w} perturb={perturb}")
+    one_step_case(synth.random_case(seed, n, f, m, h, w, perturb=perturb))
+
+
+def test_mixed_radix_beta_one_and_fixed_point():
+    say("case mixed radix beta=1 F=200 M=2")
+    one_step_case(synth.random_case(57, 8, 200, 2, 260, 280, beta=1.0))
+    say("case mixed radix consistent fixed point F=188 M=3")
+    c = synth.random_case(58, 8, 188, 3, 260, 260, consistent=True)
+    psi_g, P_g, O_g, e_g, _ = gpu_one_step(c["psi"], c["P"], c["O"], c["I"], c["pos"], 0.8)
+    assert rel(psi_g, c["psi"]) < 1e-5
+    assert rel(P_g, c["P"]) < 1e-5
+    assert e_g["eps_probe"] < 1e-5 and e_g["eps_psi"] < 1e-5
+
+
+def test_flyscan_188_strip_three_iterations():
+    """The paper-size fly scan (188x188 frames, 4 modes, 1280x1280 object) on
+    a strip of 30 views, three iterations from the initial views against
+    three oracle iterations."""
+    s = synth.flyscan_raster_188(3, n_frames=30)
+    say("case fly-scan strip of 30 views, F=188, M=4, three iterations")
+    psi0 = oracle.init_views(s.P0, s.O0, s.pos).astype(np.complex64)
+    psi_o, P_o, O_o = (psi0.astype(np.complex128), s.P0.astype(np.complex128),
+                       s.O0.astype(np.complex128))
+    for _ in range(3):
+        psi_o, P_o, O_o, e_o = oracle.iterate(psi_o, P_o, O_o, s.pos,
+                                              s.I.astype(np.float64), s.beta)
+    den = oracle.object_update(psi_o, P_o, O_o, s.pos)[1]
+    psi_g, P_g, O_g, e_g, it = gpu_one_step(psi0, s.P0, s.O0, s.I, s.pos, s.beta, n_iter=3)
+    r = (rel(psi_g, psi_o), rel_weighted(O_g, O_o, den), rel(P_g, P_o))
+    say(f"  rel L2 psi {r[0]:.2e}  O(weighted) {r[1]:.2e}  P {r[2]:.2e}")
+    assert it == 3
+    assert max(r) <= TOL, r
+    check_errors(e_g, e_o)
+
+
 @pytest.mark.parametrize("view_path", [4, 5])
 @pytest.mark.parametrize("seed,n,f,m,h,w", [(41, 29, 32, 2, 96, 90), (42, 21, 64, 3, 180, 150),
                                             (43, 13, 128, 5, 260, 250)])

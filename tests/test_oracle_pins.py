@@ -31,7 +31,7 @@ def rel(a, b):
 # ---------------------------------------------------------------------------
 # the transform
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("f", [2, 4, 8])
+@pytest.mark.parametrize("f", [2, 4, 6, 8, 12])
 def test_dft_matches_brute_force_sum(f):
     """Z~[k,l] = sum_{u,v} Z[u,v] exp(-2 pi i (ku+lv)/F), written out."""
     rng = np.random.default_rng(10 + f)
@@ -55,6 +55,18 @@ def test_dft_matches_brute_force_sum(f):
             back[u, v] = acc / (f * f)
     assert rel(dm.idft2(ref), back) < 1e-12
     assert rel(back, z) < 1e-12
+
+
+@pytest.mark.parametrize("f", [188, 200])
+def test_dft_matches_dft_matrix_at_paper_frame_sizes(f):
+    """At the paper's frame edges (4 x 47, 8 x 25) the 2-D transform is
+    W Z W^T with W[k, n] = exp(-2 pi i k n / F) built entry by entry."""
+    rng = np.random.default_rng(f)
+    z = crand(rng, f, f)
+    kn = np.outer(np.arange(f), np.arange(f)) % f
+    w = np.exp(-2j * np.pi * kn / f)
+    assert rel(dm.dft2(z), w @ z @ w.T) < 1e-12
+    assert rel(dm.idft2(w @ z @ w.T), z) < 1e-12
 
 
 def test_dft_parseval_delta_tone_inverse():

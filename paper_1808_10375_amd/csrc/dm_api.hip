@@ -87,29 +87,33 @@ int row_block(int F) {
 // row blocks per frame of the three-kernel path (one eps_psi partial each)
 int row_parts(int F) {
   switch (F) {
-    case 188: return dmk::MixRows<188>::NBLK;
-    case 200: return dmk::MixRows<200>::NBLK;
+    case 188: return dmk::Mix<188>::NBLK;
+    case 200: return dmk::Mix<200>::NBLK;
   }
   return F / row_block(F);
 }
 
-int mix_q(int F) { return F == 188 ? dmk::MixCfg<188>::Q : dmk::MixCfg<200>::Q; }
+// threads per line of the mixed-radix transforms (Q + 1)
+int mix_qt(int F) { return F == 188 ? dmk::Mix<188>::QT : dmk::Mix<200>::QT; }
 
 // columns per block of the mixed-radix column kernel: a power of two up to
-// 16 with CB * M * Q threads (rounded to whole waves) at most 1024
+// 16 with CB * M * (Q + 1) threads (rounded to whole waves) at most 1024
 int mix_cols_per_block(int F, int M) {
-  const int Q = mix_q(F);
+  const int QT = mix_qt(F);
   int p = 1;
-  while (p * 2 <= 16 && ((p * 2 * M * Q + 63) / 64) * 64 <= 1024) p *= 2;
+  while (p * 2 <= 16 && ((p * 2 * M * QT + 63) / 64) * 64 <= 1024) p *= 2;
   return p;
 }
 
-int mix_cols_threads(int F, int M, int cb) { return ((cb * M * mix_q(F) + 63) / 64) * 64; }
+int mix_cols_threads(int F, int M, int cb) { return ((cb * M * mix_qt(F) + 63) / 64) * 64; }
 
 // dynamic LDS of the mixed-radix column kernel: cb * M exchange lines of
-// Q * R + 2 complex values, the mode powers [M][cb][F] and the scale [cb][F]
+// Q * R + 2 complex values, the mode powers [M][cb][F], the scale [cb][F]
+// and the twiddle tables (F + Q complex)
 size_t mix_cols_lds_bytes(int F, int M, int cb) {
-  return (size_t)cb * M * (F + 2) * sizeof(float2) + (size_t)(M + 1) * cb * F * sizeof(float);
+  const int Q = mix_qt(F) - 1;
+  return (size_t)cb * M * (F + 2) * sizeof(float2) + (size_t)(M + 1) * cb * F * sizeof(float) +
+         (size_t)(F + Q) * sizeof(float2);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,7 +601,7 @@ dm_status launch_views_multipass(dm_ctx* c) {
 // mixed-radix line transforms.
 template <int F>
 dm_status launch_views_mixed(dm_ctx* c) {
-  using C = dmk::MixRows<F>;
+  using C = dmk::Mix<F>;
   const int M = c->M;
   hipLaunchKernelGGL(dmk::k_mix_rows_fwd<F>, dim3(c->total_views * M, C::NBLK), dim3(C::NT), 0,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M);

@@ -5,17 +5,23 @@
 // 256: row DFTs, then column DFTs with the mode sum and modulus scale and the
 // inverse column DFTs, then inverse row DFTs with the update.
 //
-// One length-F line is transformed by Q threads with one level of the
-// Cooley-Tukey split n = Q n1 + n2, k = k1 + R k2:
+// One length-F line is transformed with one level of the Cooley-Tukey split
+// n = Q n1 + n2, k = k1 + R k2:
 //   X[k1 + R k2] = sum_{n2} W_Q^{n2 k2} W_F^{n2 k1} sum_{n1} x[Q n1 + n2] W_R^{n1 k1}
-// Thread n2 holds x[Q n1 + n2] (n1 < R) in registers, does the R-point DFT
-// there, applies W_F^{n2 k1} and writes its R values to the line's LDS rows;
-// thread q then forms the Q-point DFT for k2 = q directly, X[k1 + R q] for
-// all k1, reading every row once (each row read is shared by the line's Q
-// lanes).  The inverse runs the mirror image, so every value returns to the
-// thread and register it came from, and no step needs a reordering.
-// Q-point twiddles W_Q^{(n q) mod Q} come from a table in LDS every eighth
-// step and by one complex product with W_Q^q in between.
+// by Q + 1 threads.  Thread n2 < Q holds x[Q n1 + n2] (n1 < R) in registers,
+// does the R-point DFT there, applies W_F^{n2 k1} and writes its R values to
+// row n2 of the line's LDS buffer.  The Q-point DFTs over the rows use the
+// symmetry of W_Q for odd Q: with u_n = y_n + y_{Q-n} and v_n = y_n - y_{Q-n}
+// (formed in place, 1 <= n <= (Q-1)/2) and c_n + i s_n = W_Q^{n p},
+//   Y_p     = y_0 + sum_n c_n u_n + i sum_n s_n v_n,
+//   Y_{Q-p} = y_0 + sum_n c_n u_n - i sum_n s_n v_n,
+// so thread t forms the two real-weighted sums for p = t / 2 over half of the
+// k1 range (half t % 2) and gets both outputs: a quarter of the products of
+// the direct sum, and each LDS row read serves two outputs.  The inverse runs
+// the same steps with conjugate twiddles and one more exchange, so values
+// return to the thread and register they came from.  Q-point twiddles come
+// from a table in LDS every eighth step and by one complex product with
+// W_Q^p in between.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
@@ -36,90 +42,187 @@ struct MixCfg<200> {
 };
 
 template <int F>
-struct MixRows {
+struct Mix {
   static constexpr int R = MixCfg<F>::R, Q = MixCfg<F>::Q;
-  static constexpr int RB = 256 / Q;                  // rows per block
-  static constexpr int NT = (RB * Q + 63) / 64 * 64;  // whole waves
+  static constexpr int QT = Q + 1;         // threads per line
+  static constexpr int H = R / 2;         // k1 values per pair thread
+  static constexpr int NP = (Q - 1) / 2;  // symmetric pairs of rows
+  static constexpr int LS = Q * R + 2;    // LDS line stride (complex)
+  static constexpr int RB = 256 / QT;     // rows per block of the row kernels
+  static constexpr int NT = (RB * QT + 63) / 64 * 64;  // whole waves
   static constexpr int NBLK = (F + RB - 1) / RB;      // row blocks per frame
-  static constexpr int LS = Q * R + 2;                // LDS line stride (complex)
 };
 
 // LDS tables: twl[m] = W_F^m = exp(-2 pi i m / F), m < F; twq[m] = W_Q^m.
 template <int F>
 __device__ __forceinline__ void mix_load_tables(const float2* __restrict__ tw, float2* twl,
                                                 float2* twq, int t, int nt) {
-  constexpr int R = MixCfg<F>::R, Q = MixCfg<F>::Q;
+  constexpr int R = Mix<F>::R, Q = Mix<F>::Q;
   for (int i = t; i < F; i += nt) twl[i] = tw[i];
   for (int i = t; i < Q; i += nt) twq[i] = tw[R * i];
 }
 
-// a[k1] *= W_F^{DIR n k1}
+// Thread n < Q of a line: R-point DFT of its registers, twiddle W_F^{DIR n k1},
+// row n of the line buffer.
 template <int F, int DIR>
-__device__ __forceinline__ void mix_twiddle(float2 (&a)[MixCfg<F>::R], const float2* twl, int n) {
-  constexpr int R = MixCfg<F>::R;
+__device__ __forceinline__ void mix_first(float2 (&a)[Mix<F>::R], float2* line,
+                                          const float2* twl, int n) {
+  constexpr int R = Mix<F>::R;
+  dftB<DIR, R>(a);
 #pragma unroll
   for (int k1 = 1; k1 < R; ++k1) {
     float2 w = twl[n * k1];
     if constexpr (DIR > 0) w.y = -w.y;
     a[k1] = cmul(a[k1], w);
   }
-}
-
-// a[k1] = sum_{n < Q} line[n * R + k1] W_Q^{DIR n q}
-template <int F, int DIR>
-__device__ __forceinline__ void mix_qdft(float2 (&a)[MixCfg<F>::R], const float2* line,
-                                         const float2* twq, int q) {
-  constexpr int R = MixCfg<F>::R, Q = MixCfg<F>::Q;
-  float2 acc[R];
-#pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) acc[k1] = make_float2(0.f, 0.f);
-  float2 step = twq[q];
-  if constexpr (DIR > 0) step.y = -step.y;
-  int idx = 0;  // (n * q) mod Q at the start of each group of eight
-#pragma unroll 1
-  for (int n0 = 0; n0 < Q; n0 += 8) {
-    float2 w = twq[idx];
-    if constexpr (DIR > 0) w.y = -w.y;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int n = n0 + s;
-      if (n < Q) {
-        const float4* row = reinterpret_cast<const float4*>(line + n * R);
-#pragma unroll
-        for (int h = 0; h < R / 2; ++h) {
-          const float4 v = row[h];
-          acc[2 * h].x += v.x * w.x - v.y * w.y;
-          acc[2 * h].y += v.x * w.y + v.y * w.x;
-          acc[2 * h + 1].x += v.z * w.x - v.w * w.y;
-          acc[2 * h + 1].y += v.z * w.y + v.w * w.x;
-        }
-        w = cmul(w, step);
-      }
-    }
-    idx += 8 * q;
-    idx %= Q;
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) a[k1] = acc[k1];
-}
-
-// R values of a line row to LDS as 16-byte stores
-template <int R>
-__device__ __forceinline__ void mix_store_row(float2* dst, const float2 (&a)[R]) {
-  float4* d = reinterpret_cast<float4*>(dst);
+  float4* d = reinterpret_cast<float4*>(line + n * R);
 #pragma unroll
   for (int h = 0; h < R / 2; ++h)
     d[h] = make_float4(a[2 * h].x, a[2 * h].y, a[2 * h + 1].x, a[2 * h + 1].y);
 }
 
-// (1) Z = 2 P O - psi and the DFT along rows; RB rows of one view-mode per
-// block, Q threads per row.
+// Rows n and Q - n (1 <= n <= (Q-1)/2, thread n of the line) become their
+// sum and difference, in place.
 template <int F>
-__global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_fwd(
+__device__ __forceinline__ void mix_uv(float2* line, int n) {
+  constexpr int R = Mix<F>::R, NP = Mix<F>::NP, Q = Mix<F>::Q;
+  if (n < 1 || n > NP) return;
+  float4* a = reinterpret_cast<float4*>(line + n * R);
+  float4* b = reinterpret_cast<float4*>(line + (Q - n) * R);
+#pragma unroll
+  for (int h = 0; h < R / 2; ++h) {
+    const float4 x = a[h], y = b[h];
+    a[h] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+    b[h] = make_float4(x.x - y.x, x.y - y.y, x.z - y.z, x.w - y.w);
+  }
+}
+
+// Positions (k1 + R k2) of a thread's pair outputs: lo = Y_p, hi = Y_{Q-p},
+// H consecutive values each; p = 0 has no hi.
+template <int F>
+__device__ __forceinline__ void mix_pair_pos(int t, int& ilo, int& ihi) {
+  constexpr int R = Mix<F>::R, Q = Mix<F>::Q, H = Mix<F>::H;
+  const int p = t >> 1, h = t & 1;
+  ilo = h * H + R * p;
+  ihi = p > 0 ? h * H + R * (Q - p) : -1;
+}
+
+// Q-point DFTs over the rows (after mix_uv), thread t of the line:
+// lo[k] = Y_p[k1], hi[k] = Y_{Q-p}[k1] with p = t / 2, k1 = (t % 2) H + k.
+template <int F, int DIR>
+__device__ __forceinline__ void mix_pairs(float2 (&lo)[Mix<F>::H], float2 (&hi)[Mix<F>::H],
+                                          const float2* line, const float2* twq, int t) {
+  constexpr int R = Mix<F>::R, Q = Mix<F>::Q, H = Mix<F>::H, NP = Mix<F>::NP;
+  const int p = t >> 1, h = t & 1;
+  float2 su[H], sv[H];
+#pragma unroll
+  for (int k = 0; k < H; ++k) { su[k] = make_float2(0.f, 0.f); sv[k] = make_float2(0.f, 0.f); }
+  float2 step = twq[p];
+  if constexpr (DIR > 0) step.y = -step.y;
+  int idx = p;  // (n p) mod Q at the start of each group of eight
+#pragma unroll 1
+  for (int n0 = 1; n0 <= NP; n0 += 8) {
+    float2 w = twq[idx];
+    if constexpr (DIR > 0) w.y = -w.y;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int n = n0 + s;
+      if (n <= NP) {
+        const float2* u = line + n * R + h * H;
+        const float2* v = line + (Q - n) * R + h * H;
+        float2 uu[H], vv[H];
+#pragma unroll
+        for (int k = 0; k < H; k += 2) {
+          const float4 a = *reinterpret_cast<const float4*>(u + k);
+          const float4 b = *reinterpret_cast<const float4*>(v + k);
+          uu[k] = make_float2(a.x, a.y); uu[k + 1] = make_float2(a.z, a.w);
+          vv[k] = make_float2(b.x, b.y); vv[k + 1] = make_float2(b.z, b.w);
+        }
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+          su[k].x += w.x * uu[k].x; su[k].y += w.x * uu[k].y;
+          sv[k].x += w.y * vv[k].x; sv[k].y += w.y * vv[k].y;
+        }
+        w = cmul(w, step);
+      }
+    }
+    idx += 8 * p;
+    idx %= Q;
+  }
+  const float2* y0 = line + h * H;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float2 a = make_float2(y0[k].x + su[k].x, y0[k].y + su[k].y);
+    lo[k] = make_float2(a.x - sv[k].y, a.y + sv[k].x);
+    hi[k] = make_float2(a.x + sv[k].y, a.y - sv[k].x);
+  }
+}
+
+// a thread's pair values to their rows of the line buffer
+template <int F>
+__device__ __forceinline__ void mix_put_pairs(float2* line, const float2 (&lo)[Mix<F>::H],
+                                              const float2 (&hi)[Mix<F>::H], int t) {
+  constexpr int H = Mix<F>::H;
+  int ilo, ihi;
+  mix_pair_pos<F>(t, ilo, ihi);
+#pragma unroll
+  for (int k = 0; k < H; k += 2) {
+    *reinterpret_cast<float4*>(line + ilo + k) =
+        make_float4(lo[k].x, lo[k].y, lo[k + 1].x, lo[k + 1].y);
+    if (ihi >= 0)
+      *reinterpret_cast<float4*>(line + ihi + k) =
+          make_float4(hi[k].x, hi[k].y, hi[k + 1].x, hi[k + 1].y);
+  }
+}
+
+// Thread n < Q after the inverse Q-point DFTs are back in the rows: row n,
+// twiddle W_F^{-n k1}, inverse R-point DFT; a[n1] = x[Q n1 + n].
+template <int F>
+__device__ __forceinline__ void mix_last_inv(float2 (&a)[Mix<F>::R], const float2* line,
+                                             const float2* twl, int n) {
+  constexpr int R = Mix<F>::R;
+  const float4* r = reinterpret_cast<const float4*>(line + n * R);
+#pragma unroll
+  for (int h = 0; h < R / 2; ++h) {
+    const float4 v = r[h];
+    a[2 * h] = make_float2(v.x, v.y);
+    a[2 * h + 1] = make_float2(v.z, v.w);
+  }
+#pragma unroll
+  for (int k1 = 1; k1 < R; ++k1) {
+    float2 w = twl[n * k1];
+    w.y = -w.y;
+    a[k1] = cmul(a[k1], w);
+  }
+  dftB<1, R>(a);
+}
+
+// Inverse line transform of the rows already in `line` (row k2 holds
+// X[k1 + R k2]); the caller synchronised after writing them.  Thread n < Q
+// of the line ends with a[n1] = x[Q n1 + n] (unnormalised).  Four barriers.
+template <int F>
+__device__ __forceinline__ void mix_inverse(float2 (&a)[Mix<F>::R], float2* line,
+                                            const float2* twl, const float2* twq, int t,
+                                            bool active) {
+  constexpr int H = Mix<F>::H, Q = Mix<F>::Q;
+  if (active) mix_uv<F>(line, t);
+  __syncthreads();
+  float2 lo[H], hi[H];
+  if (active) mix_pairs<F, 1>(lo, hi, line, twq, t);
+  __syncthreads();
+  if (active) mix_put_pairs<F>(line, lo, hi, t);
+  __syncthreads();
+  if (active && t < Q) mix_last_inv<F>(a, line, twl, t);
+}
+
+// (1) Z = 2 P O - psi and the DFT along rows; RB rows of one view-mode per
+// block, Q + 1 threads per row.
+template <int F>
+__global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
     const float2* __restrict__ tw, int M) {
-  using C = MixRows<F>;
-  constexpr int R = C::R, Q = C::Q, RB = C::RB, LS = C::LS, FF = F * F;
+  using C = Mix<F>;
+  constexpr int R = C::R, Q = C::Q, QT = C::QT, H = C::H, RB = C::RB, LS = C::LS, FF = F * F;
   __shared__ __align__(16) float2 xb[RB * LS];
   __shared__ float2 twl[F];
   __shared__ float2 twq[Q];
@@ -128,12 +231,13 @@ __global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_fwd(
   const ScanDev& sc = scans[vm.x];
   const int j = uni(vm.y), m = blockIdx.x % M;
   const int jm = j * M + m;
-  const int rl = t / Q, n2 = t % Q;
+  const int rl = t / QT, tl = t % QT;
   const int row = blockIdx.y * RB + rl;
   const bool active = rl < RB && row < F;
+  float2* line = xb + rl * LS;
   mix_load_tables<F>(tw, twl, twq, t, C::NT);
   float2 a[R] = {};
-  if (active) {
+  if (active && tl < Q) {
     const int W = uni(sc.W);
     const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
     const float2* __restrict__ pm = sc.psi + (size_t)jm * FF + (size_t)row * F;
@@ -141,39 +245,44 @@ __global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_fwd(
     const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
 #pragma unroll
     for (int n1 = 0; n1 < R; ++n1) {
-      const int v = Q * n1 + n2;
+      const int v = Q * n1 + tl;
       const float2 phi = cmul(Pm[v], Or[v]);
       const float2 ps = pm[v];
       a[n1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
     }
   }
   __syncthreads();  // tables
-  if (active) {
-    dftB<-1, R>(a);
-    mix_twiddle<F, -1>(a, twl, n2);
-    mix_store_row<R>(xb + rl * LS + n2 * R, a);
-  }
+  if (active && tl < Q) mix_first<F, -1>(a, line, twl, tl);
+  __syncthreads();
+  if (active) mix_uv<F>(line, tl);
   __syncthreads();
   if (active) {
-    mix_qdft<F, -1>(a, xb + rl * LS, twq, n2);
-    float2* __restrict__ Tr = sc.tspec + (size_t)jm * FF + (size_t)row * F + R * n2;
+    float2 lo[H], hi[H];
+    mix_pairs<F, -1>(lo, hi, line, twq, tl);
+    int ilo, ihi;
+    mix_pair_pos<F>(tl, ilo, ihi);
+    float2* __restrict__ Tr = sc.tspec + (size_t)jm * FF + (size_t)row * F;
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) Tr[k1] = a[k1];
+    for (int k = 0; k < H; ++k) {
+      Tr[ilo + k] = lo[k];
+      if (ihi >= 0) Tr[ihi + k] = hi[k];
+    }
   }
 }
 
 // (2) DFT along CB columns of every mode of one view, the mode sum, the
 // modulus scale and the inverse DFT along the columns, in place in the
-// spectrum buffer.  Thread (c, n2, m) with c fastest; dynamic LDS: CB * M
-// exchange lines, then the mode powers s [M][CB][F] and the scale g [CB][F].
+// spectrum buffer.  Thread (c, tl, m) with c fastest.  All LDS is dynamic,
+// so the line buffers start at offset 0 and their 16-byte accesses are
+// aligned: CB * M line buffers, the mode powers s [M][CB][F], the scale g
+// [CB][F], then the twiddle tables (F + Q complex).
 template <int F>
 __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ scans,
                                                    const int2* __restrict__ vmap,
                                                    const float2* __restrict__ tw, int M, int CB) {
-  constexpr int R = MixCfg<F>::R, Q = MixCfg<F>::Q, LS = MixRows<F>::LS, FF = F * F;
+  using C = Mix<F>;
+  constexpr int R = C::R, Q = C::Q, QT = C::QT, H = C::H, LS = C::LS, FF = F * F;
   extern __shared__ __align__(16) float2 dyn[];
-  __shared__ float2 twl[F];
-  __shared__ float2 twq[Q];
   const int t = threadIdx.x;
   const int nblk = (F + CB - 1) / CB;
   const int slot = xcd_group_slot(blockIdx.x, gridDim.x);
@@ -183,32 +292,38 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
   const int col0 = (slot % nblk) * CB;
   const int c = t % CB;
   const int rest = t / CB;
-  const int n2 = rest % Q;
-  const int m = rest / Q;
+  const int tl = rest % QT;
+  const int m = rest / QT;
   const bool active = m < M && col0 + c < F;
-  const int line = m * CB + c;
-  float2* xl = dyn + (size_t)line * LS;
+  const int line_id = m * CB + c;
+  float2* line = dyn + (size_t)line_id * LS;
   float* s = reinterpret_cast<float*>(dyn + (size_t)CB * M * LS);
   float* g = s + (size_t)M * CB * F;
+  float2* twl = reinterpret_cast<float2*>(g + (size_t)CB * F);  // F even: 8-byte aligned
+  float2* twq = twl + F;
   float2* __restrict__ Tm = sc.tspec + ((size_t)j * M + m) * FF + col0 + c;
   mix_load_tables<F>(tw, twl, twq, t, blockDim.x);
   float2 a[R] = {};
-  if (active) {
+  if (active && tl < Q) {
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) a[n1] = Tm[(size_t)(Q * n1 + n2) * F];
+    for (int n1 = 0; n1 < R; ++n1) a[n1] = Tm[(size_t)(Q * n1 + tl) * F];
   }
   __syncthreads();
-  if (active) {
-    dftB<-1, R>(a);
-    mix_twiddle<F, -1>(a, twl, n2);
-    mix_store_row<R>(xl + n2 * R, a);
-  }
+  if (active && tl < Q) mix_first<F, -1>(a, line, twl, tl);
   __syncthreads();
+  if (active) mix_uv<F>(line, tl);
+  __syncthreads();
+  float2 lo[H], hi[H];
+  int ilo, ihi;
+  mix_pair_pos<F>(tl, ilo, ihi);
   if (active) {
-    mix_qdft<F, -1>(a, xl, twq, n2);  // a[k1] = spectrum at row k1 + R n2
-    float* sl = s + (size_t)line * F + R * n2;
+    mix_pairs<F, -1>(lo, hi, line, twq, tl);  // spectrum at rows ilo + k, ihi + k
+    float* sl = s + (size_t)line_id * F;
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) sl[k1] = cabs2(a[k1]);
+    for (int k = 0; k < H; ++k) {
+      sl[ilo + k] = cabs2(lo[k]);
+      if (ihi >= 0) sl[ihi + k] = cabs2(hi[k]);
+    }
   }
   __syncthreads();
   // one thread per pixel of the block's columns: sum over modes, scale
@@ -225,19 +340,20 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
   }
   __syncthreads();
   if (active) {
-    const float* gl = g + c * F + R * n2;
+    const float* gl = g + c * F;
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) a[k1] = cscale(a[k1], gl[k1]);
-    // the forward reads of this line finished before the barriers above
-    mix_store_row<R>(xl + n2 * R, a);
+    for (int k = 0; k < H; ++k) {
+      lo[k] = cscale(lo[k], gl[ilo + k]);
+      if (ihi >= 0) hi[k] = cscale(hi[k], gl[ihi + k]);
+    }
+    // the forward reads of this line ended before the barriers above
+    mix_put_pairs<F>(line, lo, hi, tl);
   }
   __syncthreads();
-  if (active) {
-    mix_qdft<F, 1>(a, xl, twq, n2);
-    mix_twiddle<F, 1>(a, twl, n2);
-    dftB<1, R>(a);
+  mix_inverse<F>(a, line, twl, twq, tl, active);
+  if (active && tl < Q) {
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) Tm[(size_t)(Q * n1 + n2) * F] = a[n1];
+    for (int n1 = 0; n1 < R; ++n1) Tm[(size_t)(Q * n1 + tl) * F] = a[n1];
   }
 }
 
@@ -245,11 +361,11 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
 // object numerator sum_m conj(P_m) psi'_m and the eps_psi partial sums; all
 // modes of RB rows per block.
 template <int F>
-__global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_inv(
+__global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
     const float2* __restrict__ tw, int M) {
-  using C = MixRows<F>;
-  constexpr int R = C::R, Q = C::Q, RB = C::RB, LS = C::LS, NT = C::NT, FF = F * F;
+  using C = Mix<F>;
+  constexpr int R = C::R, Q = C::Q, QT = C::QT, RB = C::RB, LS = C::LS, NT = C::NT, FF = F * F;
   __shared__ __align__(16) float2 xb[RB * LS];
   __shared__ float2 twl[F];
   __shared__ float2 twq[Q];
@@ -258,9 +374,11 @@ __global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_inv(
   const int2 vm = vmap[blockIdx.x];
   const ScanDev& sc = scans[vm.x];
   const int j = uni(vm.y);
-  const int rl = t / Q, n2 = t % Q;
+  const int rl = t / QT, tl = t % QT;
   const int row = blockIdx.y * RB + rl;
   const bool active = rl < RB && row < F;
+  const bool owner = active && tl < Q;  // holds pixels Q n1 + tl of the row
+  float2* line = xb + rl * LS;
   const int W = uni(sc.W);
   const float beta = sc.beta;
   const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
@@ -272,25 +390,28 @@ __global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_inv(
   float e_d = 0.f, e_n = 0.f;
   for (int m = 0; m < M; ++m) {
     const size_t base = ((size_t)j * M + m) * FF + (size_t)row * F;
-    float2 a[R] = {};
-    if (active) {
-      const float2* __restrict__ Tr = sc.tspec + base + R * n2;
+    float4 x[R / 2] = {};
+    if (owner) {
+      const float4* __restrict__ Tr = reinterpret_cast<const float4*>(sc.tspec + base + R * tl);
 #pragma unroll
-      for (int k1 = 0; k1 < R; ++k1) a[k1] = Tr[k1];
+      for (int h = 0; h < R / 2; ++h) x[h] = Tr[h];
     }
-    __syncthreads();  // the previous mode's reads of xb (and the tables)
-    if (active) mix_store_row<R>(xb + rl * LS + n2 * R, a);
+    __syncthreads();  // the previous mode's reads of the line buffer (and the tables)
+    if (owner) {
+      float4* d = reinterpret_cast<float4*>(line + R * tl);
+#pragma unroll
+      for (int h = 0; h < R / 2; ++h) d[h] = x[h];
+    }
     __syncthreads();
-    if (active) {
-      mix_qdft<F, 1>(a, xb + rl * LS, twq, n2);
-      mix_twiddle<F, 1>(a, twl, n2);
-      dftB<1, R>(a);  // a[n1] = Z' at column Q n1 + n2
+    float2 a[R] = {};
+    mix_inverse<F>(a, line, twl, twq, tl, active);  // a[n1] = Z' at column Q n1 + tl
+    if (owner) {
       float2* __restrict__ pm = sc.psi + base;
       const float2* __restrict__ Pm = sc.P + (size_t)m * FF + (size_t)row * F;
       float2 pr[R], ov[R], pv[R];
 #pragma unroll
       for (int n1 = 0; n1 < R; ++n1) {
-        const int v = Q * n1 + n2;
+        const int v = Q * n1 + tl;
         pr[n1] = Pm[v];
         ov[n1] = Or[v];
         pv[n1] = pm[v];
@@ -300,17 +421,17 @@ __global__ __launch_bounds__(MixRows<F>::NT) void k_mix_rows_inv(
         const float2 phi = cmul(pr[n1], ov[n1]);
         const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
         const float2 pn = cadd(pv[n1], d);
-        pm[Q * n1 + n2] = pn;
+        pm[Q * n1 + tl] = pn;
         e_d += cabs2(d);
         e_n += cabs2(pn);
         oacc[n1] = cadd(oacc[n1], cmulc(pr[n1], pn));
       }
     }
   }
-  if (active) {
+  if (owner) {
     float2* __restrict__ oj = sc.opart + (size_t)j * FF + (size_t)row * F;
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) oj[Q * n1 + n2] = oacc[n1];
+    for (int n1 = 0; n1 < R; ++n1) oj[Q * n1 + tl] = oacc[n1];
   }
   block_sum2<NT>(e_d, e_n, red);
   if (t == 0) {

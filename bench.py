@@ -246,6 +246,39 @@ def bench_psi_error_last(scan, steps: int, warmup: int):
             "eps_psi": f"formed in 1 of the {steps} timed iterations"}
 
 
+def bench_probe_first(scan, steps: int, warmup: int):
+    """The headline scan in the swapped update order of Section III
+    (DM_FLAG_PROBE_FIRST: probe from the new views and the current object,
+    then object from the new views and the new probe), with the phase
+    times."""
+    import torch
+    from paper_1808_10375_amd import dm
+    dev = torch.device("cuda:0")
+    n, m = scan.n_frames, scan.n_modes
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        ctx = dm.DMContext(torch.from_numpy(scan.I).to(dev), scan.pos,
+                           torch.from_numpy(scan.P0).to(dev), torch.from_numpy(scan.O0).to(dev),
+                           beta=scan.beta, stream=stream,
+                           flags=dm.DM_FLAG_PROBE_FIRST | dm.DM_FLAG_PHASE_TIMING)
+        ctx.iterate(warmup)
+        ctx.phase_times()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ctx.iterate(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        phases, n_timed = ctx.phase_times()
+        err = ctx.errors()["eps_probe"]
+        ctx.free()
+    return {"workload": "the same scan as the headline line",
+            "value": n * m / (elapsed / steps), "unit": "frame·mode/s",
+            "ms_per_step": 1e3 * elapsed / steps,
+            "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
+            "err_after": {"iterations": warmup + steps, "eps_probe": err}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,6 +430,7 @@ def main():
     if (not args.no_forms and args.config == 1 and not args.paper_frame
             and args.precision == "fp32"):
         out["forms"] = {"psi_error_last": bench_psi_error_last(scan, args.steps, args.warmup),
+                        "probe_first": bench_probe_first(scan, args.steps, args.warmup),
                         "batched": bench_batched(args.steps, args.warmup, args.conv_iters),
                         "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,
                                                errs[-1])}

@@ -111,10 +111,24 @@ typedef enum {
                                     not formed there and eps_psi is reported
                                     as NaN.                                 */
 
-/* Phases of one iteration, in launch order (indices of dm_phase_times). */
+#define DM_FLAG_PROBE_FIRST 16u  /* overlap projection in the swapped order
+                                    the paper describes (Section III, the
+                                    remark on the object embedding): the
+                                    probe (Eq. 4) from the new views and the
+                                    current object, then the object (Eq. 5)
+                                    from the new views and the new probe.
+                                    Default: object first, then probe from
+                                    the new object.  Costs one more read of
+                                    psi' (the object numerators are formed
+                                    again with the new probe).              */
+
+/* Phases of one iteration, in launch order (indices of dm_phase_times;
+ * with DM_FLAG_PROBE_FIRST the two probe phases run before the object
+ * phase). */
 #define DM_PHASE_VIEWS 0         /* Eq. 3 with F_c: exit waves, transforms,
                                     modulus projection, view update         */
-#define DM_PHASE_OBJECT 1        /* Eq. 5: object gather                     */
+#define DM_PHASE_OBJECT 1        /* Eq. 5: object gather (probe first: with
+                                    the numerators formed again before it)  */
 #define DM_PHASE_PROBE_PARTIAL 2 /* Eq. 4: per-chunk probe sums              */
 #define DM_PHASE_PROBE_FINAL 3   /* Eq. 4: division, next mode power        */
 #define DM_PHASE_ERRORS 4        /* Eq. 6: error norms into the ring        */

@@ -184,16 +184,23 @@ def rel_change(new, old, mask=None) -> float:
 # ---------------------------------------------------------------------------
 # one iteration and a run
 # ---------------------------------------------------------------------------
-def iterate(psi, P, O, pos, I, beta):
+def iterate(psi, P, O, pos, I, beta, probe_first: bool = False):
     """One DM iteration: views (Eq. 3), then object (Eq. 5) from the new
     views and the old probe, then probe (Eq. 4) from the new views and the
-    new object.  Returns (psi', P', O', errors)."""
+    new object.  With probe_first, the order Section III describes as an
+    optimisation: probe (Eq. 4) from the new views and the old object, then
+    object (Eq. 5) from the new views and the new probe.
+    Returns (psi', P', O', errors)."""
     pos = np.asarray(pos)
     P = np.asarray(P, dtype=np.complex128)
     O = np.asarray(O, dtype=np.complex128)
     psi_new = view_update(psi, P, O, pos, I, beta)
-    O_new, den_o = object_update(psi_new, P, O, pos)
-    P_new, _ = probe_update(psi_new, O_new, P, pos)
+    if probe_first:
+        P_new, _ = probe_update(psi_new, O, P, pos)
+        O_new, den_o = object_update(psi_new, P_new, O, pos)
+    else:
+        O_new, den_o = object_update(psi_new, P, O, pos)
+        P_new, _ = probe_update(psi_new, O_new, P, pos)
     errors = {
         "eps_psi": rel_change(psi_new, psi),
         "eps_obj": rel_change(O_new, O, den_o > 0),

@@ -17,6 +17,7 @@
 #include "dm_kernels.hpp"
 #include "dm_mfma.hpp"
 #include "dm_mixed.hpp"
+#include "dm_order.hpp"
 
 using dmk::DevErrors;
 using dmk::ScanDev;
@@ -248,7 +249,8 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     return DM_E_UNSUPPORTED;
   }
   if (d->flags &
-      ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH | DM_FLAG_PSI_ERROR_LAST)) {
+      ~(DM_FLAG_MULTIPASS | DM_FLAG_PHASE_TIMING | DM_FLAG_GRAPH | DM_FLAG_PSI_ERROR_LAST |
+        DM_FLAG_PROBE_FIRST)) {
     why = "unknown flag bits";
     return DM_E_ARG;
   }
@@ -780,25 +782,44 @@ dm_status launch_iteration(dm_ctx* c, bool psi_err) {
   bool psi_valid = true;
   DM_TRY(launch_views(c, psi_err, &psi_valid));
   DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
-  if (c->tune.obj_tile == 16)
-    hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
-                       c->scan_dev(), c->tmap(), F);
-  else
-    hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
-                       c->scan_dev(), c->tmap(), F);
-  DM_LAUNCHED(c, "k_object");
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_PROBE_PARTIAL, &mk));
-  hipLaunchKernelGGL(dmk::k_probe_partial, dim3(nb, c->total_chunks), dim3(256), 0, c->stream,
-                     c->scan_dev(), c->cmap(), M, F);
-  DM_LAUNCHED(c, "k_probe_partial");
-  DM_TRY(phase_end(c, mk));
-  DM_TRY(phase_begin(c, DM_PHASE_PROBE_FINAL, &mk));
-  hipLaunchKernelGGL(dmk::k_probe_final, dim3(nb, n), dim3(256), 0, c->stream, c->scan_dev(),
-                     M, FF);
-  DM_LAUNCHED(c, "k_probe_final");
-  DM_TRY(phase_end(c, mk));
+  // Eq. 5 gather of the per-view numerators (with DM_FLAG_PROBE_FIRST the
+  // numerators are formed again with the new probe first)
+  auto object = [&]() -> dm_status {
+    DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
+    if (c->flags & DM_FLAG_PROBE_FIRST) {
+      hipLaunchKernelGGL(dmk::k_view_numerators, dim3(c->total_views, nb), dim3(256), 0,
+                         c->stream, c->scan_dev(), c->vmap(), M, FF);
+      DM_LAUNCHED(c, "k_view_numerators");
+    }
+    if (c->tune.obj_tile == 16)
+      hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
+                         c->scan_dev(), c->tmap(), F);
+    else
+      hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
+                         c->scan_dev(), c->tmap(), F);
+    DM_LAUNCHED(c, "k_object");
+    return phase_end(c, mk);
+  };
+  // Eq. 4 from the new views and the object as it stands
+  auto probe = [&]() -> dm_status {
+    DM_TRY(phase_begin(c, DM_PHASE_PROBE_PARTIAL, &mk));
+    hipLaunchKernelGGL(dmk::k_probe_partial, dim3(nb, c->total_chunks), dim3(256), 0, c->stream,
+                       c->scan_dev(), c->cmap(), M, F);
+    DM_LAUNCHED(c, "k_probe_partial");
+    DM_TRY(phase_end(c, mk));
+    DM_TRY(phase_begin(c, DM_PHASE_PROBE_FINAL, &mk));
+    hipLaunchKernelGGL(dmk::k_probe_final, dim3(nb, n), dim3(256), 0, c->stream, c->scan_dev(),
+                       M, FF);
+    DM_LAUNCHED(c, "k_probe_final");
+    return phase_end(c, mk);
+  };
+  if (c->flags & DM_FLAG_PROBE_FIRST) {
+    DM_TRY(probe());
+    DM_TRY(object());
+  } else {
+    DM_TRY(object());
+    DM_TRY(probe());
+  }
   DM_TRY(phase_begin(c, DM_PHASE_ERRORS, &mk));
   hipLaunchKernelGGL(dmk::k_errors, dim3(n), dim3(256), 0, c->stream, c->scan_dev(), nb, M,
                      c->flags_dev(), psi_valid ? 1 : 0);

@@ -31,6 +31,7 @@ DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 
 DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
 DM_FLAG_GRAPH = 4         # capture one iteration into a hipGraph and replay it
 DM_FLAG_PSI_ERROR_LAST = 8  # eps_psi in the last iteration of a call only (psi-free update)
+DM_FLAG_PROBE_FIRST = 16  # probe update before the object update (Section III's swapped order)
 DM_VIEWS_FUSED = 0            # dm_tuning.view_path values
 DM_VIEWS_THREE_KERNEL = 1
 DM_VIEWS_STREAMED = 2

@@ -53,7 +53,7 @@ def test_workspace_bytes_valid_and_invalid():
     assert dm.dm_workspace_bytes(desc(n_frames=20)) > n
     for bad in (dict(frame=48), dict(frame=8), dict(frame=512), dict(n_modes=0),
                 dict(n_modes=17), dict(beta=1.5), dict(beta=-0.1), dict(obj_h=16),
-                dict(n_frames=0), dict(precision=7), dict(flags=16), dict(flags=6)):
+                dict(n_frames=0), dict(precision=7), dict(flags=32), dict(flags=6)):
         assert dm.dm_workspace_bytes(desc(**bad)) == 0, bad
     # the paper's frame edges 188 and 200 run the three-kernel path: psi
     # and the spectrum buffer

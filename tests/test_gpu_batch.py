@@ -126,6 +126,45 @@ def test_graph_replays_equal_eager_launches():
     e.free()
 
 
+def test_probe_first_batch_graphs_equal_eager_and_oracle():
+    """DM_FLAG_PROBE_FIRST on a batch of two scans: after one iteration the
+    probe and object match the oracle in the same order; graph replays equal
+    eager launches bitwise after one and after three iterations."""
+    torch = _torch()
+    from paper_1808_10375_amd import dm
+    scans = uneven_scans(seed=75, sizes=(19, 26), f=64, m=2, objs=(150, 130))
+    say("case probe-first batch: graph vs eager over 3 iterations, oracle after 1")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = dm.DMBatch(scans, flags=dm.DM_FLAG_GRAPH | dm.DM_FLAG_PROBE_FIRST, stream=stream)
+    e = dm.DMBatch(scans, flags=dm.DM_FLAG_PROBE_FIRST)
+    for n_it in (1, 2):
+        g.iterate(n_it)
+        e.iterate(n_it)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for s, sc in enumerate(scans):
+            og, oe, pg, pe = g.object(s), e.object(s), g.probe(s), e.probe(s)
+            torch.cuda.synchronize()
+            assert torch.equal(og, oe) and torch.equal(pg, pe), (n_it, s)
+            if n_it != 1:
+                continue
+            psi0 = oracle.init_views(sc["P0"], sc["O0"], sc["pos"])
+            psi, P, O, e_o = oracle.iterate(psi0, sc["P0"], sc["O0"], sc["pos"],
+                                            sc["I"].astype(np.float64), sc["beta"],
+                                            probe_first=True)
+            den = oracle.object_update(psi, P, sc["O0"], sc["pos"])[1]
+            Og = oe.cpu().numpy()
+            wrel = float(np.sqrt(np.sum(den * np.abs(Og - O) ** 2) /
+                                 np.sum(den * np.abs(O) ** 2)))
+            say(f"  scan {s}: rel P {rel(pe.cpu().numpy(), P):.1e} O(weighted) {wrel:.1e}")
+            assert rel(pe.cpu().numpy(), P) <= 1e-5 and wrel <= 1e-5
+            eg = e.error_history(s, 1, 1)[0]
+            assert abs(eg["eps_probe"] - e_o["eps_probe"]) <= 1e-4 * e_o["eps_probe"]
+    g.free()
+    e.free()
+
+
 def test_graphs_with_psi_error_last_equal_eager_launches():
     """DM_FLAG_PSI_ERROR_LAST with graph replay: each context keeps one graph
     without and one with the eps_psi partials (the last iteration of a

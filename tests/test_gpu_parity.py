@@ -18,6 +18,7 @@ from paper_1808_10375_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+PROBE_FIRST = 16  # DM_FLAG_PROBE_FIRST
 
 
 def _torch():
@@ -86,11 +87,13 @@ def one_step_case(case, flags=0, tol=TOL, view_path=None):
     the quotient there."""
     psi, P, O, I, pos, beta = (case["psi"], case["P"], case["O"], case["I"], case["pos"],
                                case["beta"])
+    probe_first = bool(flags & PROBE_FIRST)
     psi_o, P_o, O_o, e_o = oracle.iterate(psi.astype(np.complex128), P.astype(np.complex128),
                                           O.astype(np.complex128), pos, I.astype(np.float64),
-                                          beta)
-    den_o = oracle.object_update(psi_o, P.astype(np.complex128), O.astype(np.complex128),
-                                 pos)[1]
+                                          beta, probe_first=probe_first)
+    # the Eq. 5 denominator of the probe the object was formed with
+    den_o = oracle.object_update(psi_o, P_o if probe_first else P.astype(np.complex128),
+                                 O.astype(np.complex128), pos)[1]
     psi_g, P_g, O_g, e_g, it = gpu_one_step(psi, P, O, I, pos, beta, flags,
                                             view_path=view_path)
     r = (rel(psi_g, psi_o), rel_weighted(O_g, O_o, den_o), rel(P_g, P_o), rel(O_g, O_o))
@@ -274,6 +277,19 @@ def test_flyscan_256_strip_one_step():
     say("case fly-scan strip of 24 views, F=256, M=8")
     psi0 = oracle.init_views(s.P0, s.O0, s.pos).astype(np.complex64)
     one_step_case(dict(psi=psi0, P=s.P0, O=s.O0, I=s.I, pos=s.pos, beta=0.8))
+
+
+@pytest.mark.parametrize("seed,n,f,m,h,w,view_path", [(61, 23, 32, 2, 90, 80, None),
+                                                      (62, 13, 128, 3, 260, 250, None),
+                                                      (63, 11, 64, 2, 160, 150, 1),
+                                                      (64, 7, 188, 2, 260, 260, None)])
+def test_one_step_probe_first_order(seed, n, f, m, h, w, view_path):
+    """Section III's swapped order (DM_FLAG_PROBE_FIRST): probe from the new
+    views and the old object, then object from the new views and the new
+    probe, against the oracle in the same order."""
+    say(f"case probe first seed={seed} N={n} F={f} M={m} obj={h}x{w} view_path={view_path}")
+    flags = PROBE_FIRST | (1 if view_path == 1 else 0)
+    one_step_case(synth.random_case(seed, n, f, m, h, w), flags=flags, view_path=view_path)
 
 
 MIXED = [

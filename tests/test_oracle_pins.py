@@ -220,15 +220,40 @@ def test_probe_update_is_weighted_least_squares():
 # ---------------------------------------------------------------------------
 # the whole iteration
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("probe_first", [False, True])
 @pytest.mark.parametrize("beta", [0.0, 0.8, 1.0])
-def test_dm_fixed_point_on_consistent_data(beta):
+def test_dm_fixed_point_on_consistent_data(beta, probe_first):
     psi, P, O, pos, I = _consistent()
-    psi2, P2, O2, e = dm.iterate(psi, P, O, pos, I, beta)
+    psi2, P2, O2, e = dm.iterate(psi, P, O, pos, I, beta, probe_first=probe_first)
     assert rel(psi2, psi) < 1e-12
     assert rel(P2, P) < 1e-12
     den = dm.object_update(psi, P, O, pos)[1]
     assert rel(O2[den > 0], O[den > 0]) < 1e-12
     assert e["eps_psi"] < 1e-12 and e["eps_obj"] < 1e-12 and e["eps_probe"] < 1e-12
+
+
+def test_update_orders_on_a_single_view():
+    """One view, one mode: with the object updated first, O' = psi'/P on the
+    window and then P' = psi'/O' = P; with the probe first (Section III's
+    swapped order), P' = psi'/O and then O' = psi'/P' = O on the window,
+    while pixels outside the window keep their value in both orders."""
+    rng = np.random.default_rng(12)
+    f = 6
+    P = crand(rng, 1, f, f)
+    O = crand(rng, 9, 10) + 2.0
+    pos = np.array([[2, 3]])
+    psi = crand(rng, 1, 1, f, f)
+    I = np.abs(crand(rng, 1, f, f)) ** 2
+    psi_new = dm.view_update(psi, P, O, pos, I, 0.8)
+    win = (slice(2, 8), slice(3, 9))
+    _, P1, O1, _ = dm.iterate(psi, P, O, pos, I, 0.8)
+    assert rel(O1[win], psi_new[0, 0] / P[0]) < 1e-12
+    assert rel(P1, P) < 1e-12
+    _, P2, O2, _ = dm.iterate(psi, P, O, pos, I, 0.8, probe_first=True)
+    assert rel(P2[0], psi_new[0, 0] / O[win]) < 1e-12
+    assert rel(O2[win], O[win]) < 1e-12
+    for Ox in (O1, O2):
+        assert np.array_equal(Ox[:2], O[:2]) and np.array_equal(Ox[:, :3], O[:, :3])
 
 
 def _random_state(seed=9, n=5, m=2, f=8, h=18, w=21):

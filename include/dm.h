@@ -234,6 +234,13 @@ dm_status dm_get_object(dm_ctx* ctx, void* dst_dev);
 /* Enqueue a device-to-device copy of the current probe, complex64 [M][F][F]. */
 dm_status dm_get_probe(dm_ctx* ctx, void* dst_dev);
 
+/* Synchronise and return the power of each probe mode, sum over pixels of
+ * |P_k|^2 (FP64 sums on the device), k < M, in power_host[M].  The paper
+ * (Section II, after Eq. 6) picks the number of probe modes by adding
+ * modes in trial runs while each one carries at least 1% of the total
+ * intensity; its share is power[k] / sum(power). */
+dm_status dm_mode_power(dm_ctx* ctx, double* power_host);
+
 /* Synchronise and return the error norms of the latest iteration
  * (iter = 0 and zeros before the first).  DM_E_NUMERIC if any is not
  * finite. */
@@ -287,6 +294,7 @@ dm_status dm_scan_get_object(dm_ctx* ctx, int32_t scan, void* dst_dev);
 dm_status dm_scan_get_probe(dm_ctx* ctx, int32_t scan, void* dst_dev);
 dm_status dm_scan_error_history(dm_ctx* ctx, int32_t scan, int32_t first,
                                 int32_t count, dm_errors* out_host);
+dm_status dm_scan_mode_power(dm_ctx* ctx, int32_t scan, double* power_host);
 
 /* ---- warm start ------------------------------------------------------------ */
 /* Replace the object with patches stitched by the object update (Section II,

@@ -18,6 +18,7 @@
 #include "dm_mfma.hpp"
 #include "dm_mixed.hpp"
 #include "dm_order.hpp"
+#include "dm_modes.hpp"
 
 using dmk::DevErrors;
 using dmk::ScanDev;
@@ -122,7 +123,7 @@ size_t mix_cols_lds_bytes(int F, int M, int cb) {
 // ---------------------------------------------------------------------------
 struct ScanLayout {
   size_t psi, opart, gscr, tspec, P, O, D, num_part, den_part, err_psi, err_obj, err_probe,
-      ring, counter, pos, order, tile_ptr, tile_views, bytes;
+      ring, counter, mode_pow, pos, order, tile_ptr, tile_views, bytes;
   int ntiles16, nnz16, n_psi_parts_fused, n_psi_parts_multi;
 };
 
@@ -164,6 +165,7 @@ ScanLayout scan_layout(const dm_desc& d) {
   L.err_probe = take((size_t)n_pblk((int)F) * M * 2 * 4);
   L.ring = take(sizeof(DevErrors) * dmk::kRing);
   L.counter = take(sizeof(int));
+  L.mode_pow = take(DM_MAX_MODES * sizeof(double));
   L.pos = take(N * 2 * 4);
   L.order = take(N * 4);
   L.tile_ptr = take(((size_t)L.ntiles16 + 1) * 4);
@@ -1207,6 +1209,25 @@ dm_status dm_scan_get_probe(dm_ctx* c, int32_t scan, void* dst) {
                            (size_t)S.d.n_modes * S.d.frame * S.d.frame * 8,
                            hipMemcpyDeviceToDevice, c->stream));
   return DM_OK;
+}
+
+dm_status dm_scan_mode_power(dm_ctx* c, int32_t scan, double* power_host) {
+  dm_status s = check_scan(c, scan);
+  if (s != DM_OK) return s;
+  if (!power_host) { c->err = "power_host is NULL"; return DM_E_ARG; }
+  const auto& S = c->scans[scan];
+  double* dev = c->sat<double>(scan, S.L.mode_pow);
+  hipLaunchKernelGGL(dmk::k_mode_sums, dim3(S.d.n_modes), dim3(256), 0, c->stream,
+                     c->sat<float2>(scan, S.L.P), S.d.frame * S.d.frame, dev);
+  DM_LAUNCHED(c, "k_mode_sums");
+  DM_HIP(c, hipMemcpyAsync(power_host, dev, (size_t)S.d.n_modes * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  DM_HIP(c, hipStreamSynchronize(c->stream));
+  return DM_OK;
+}
+
+dm_status dm_mode_power(dm_ctx* c, double* power_host) {
+  return dm_scan_mode_power(c, 0, power_host);
 }
 
 dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {

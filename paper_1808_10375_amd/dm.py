@@ -48,7 +48,8 @@ EXPORTED = [
     "dm_free", "dm_status_str", "dm_last_error", "dm_phase_times",
     "dm_batch_workspace_bytes", "dm_batch_init", "dm_n_scans", "dm_scan_get_object",
     "dm_scan_get_probe", "dm_scan_error_history", "dm_get_tuning", "dm_set_tuning",
-    "dm_autotune", "dm_warm_start", "dm_scan_warm_start",
+    "dm_autotune", "dm_warm_start", "dm_scan_warm_start", "dm_mode_power",
+    "dm_scan_mode_power",
 ]
 
 
@@ -135,6 +136,10 @@ def lib():
     L.dm_scan_get_probe.restype = i32
     L.dm_scan_error_history.argtypes = [vp, i32, i32, i32, ctypes.POINTER(dm_errors)]
     L.dm_scan_error_history.restype = i32
+    L.dm_mode_power.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.dm_mode_power.restype = i32
+    L.dm_scan_mode_power.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    L.dm_scan_mode_power.restype = i32
     L.dm_get_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
     L.dm_get_tuning.restype = i32
     L.dm_set_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
@@ -232,6 +237,18 @@ def dm_error_history(ctx, first: int, count: int):
     arr = (dm_errors * max(count, 1))()
     _check(lib().dm_error_history(ctx, int(first), int(count), arr), ctx)
     return [arr[i] for i in range(count)]
+
+
+def dm_scan_mode_power(ctx, scan: int, n_modes: int):
+    arr = (ctypes.c_double * n_modes)()
+    _check(lib().dm_scan_mode_power(ctx, int(scan), arr), ctx)
+    return [float(arr[i]) for i in range(n_modes)]
+
+
+def dm_mode_power(ctx, n_modes: int):
+    arr = (ctypes.c_double * n_modes)()
+    _check(lib().dm_mode_power(ctx, arr), ctx)
+    return [float(arr[i]) for i in range(n_modes)]
 
 
 def dm_iterations(ctx) -> int:
@@ -388,6 +405,10 @@ class DMContext:
             count = dm_iterations(self.ctx) - first + 1
         return [e.to_dict(self.n_modes) for e in dm_error_history(self.ctx, first, count)]
 
+    def mode_power(self):
+        """sum over pixels of |P_k|^2 for every probe mode (synchronises)"""
+        return dm_mode_power(self.ctx, self.n_modes)
+
     def state(self):
         import torch
         d = self.desc
@@ -492,6 +513,9 @@ class DMBatch:
             count = dm_iterations(self.ctx) - first + 1
         m = self.descs[scan].n_modes
         return [e.to_dict(m) for e in dm_scan_error_history(self.ctx, scan, first, count)]
+
+    def mode_power(self, scan: int):
+        return dm_scan_mode_power(self.ctx, scan, self.descs[scan].n_modes)
 
     def tuning(self) -> dict:
         return dm_get_tuning(self.ctx).to_dict()

@@ -292,6 +292,33 @@ def test_one_step_probe_first_order(seed, n, f, m, h, w, view_path):
     one_step_case(synth.random_case(seed, n, f, m, h, w), flags=flags, view_path=view_path)
 
 
+@pytest.mark.parametrize("seed,n,f,m,h,w", [(71, 19, 64, 3, 150, 140), (72, 6, 188, 2, 260, 250)])
+def test_mode_power_matches_the_probe_and_the_oracle(seed, n, f, m, h, w):
+    """dm_mode_power (the quantity of the paper's 1% rule for the number of
+    probe modes): sum over pixels of |P_k|^2 of the library's own probe, and
+    of the oracle's probe after the same iteration."""
+    torch = _torch()
+    from paper_1808_10375_amd import dm
+    say(f"case mode power seed={seed} N={n} F={f} M={m}")
+    c = synth.random_case(seed, n, f, m, h, w)
+    dev = torch.device("cuda:0")
+    Pt = torch.from_numpy(c["P"]).to(dev)
+    Ot = torch.from_numpy(c["O"]).to(dev)
+    ctx = dm.DMContext(torch.from_numpy(c["I"]).to(dev), c["pos"], Pt, Ot, beta=c["beta"])
+    ctx.set_state(torch.from_numpy(c["psi"]).to(dev), Pt, Ot, 0)
+    ctx.iterate(1)
+    pw = np.array(ctx.mode_power())
+    Pg = ctx.probe().cpu().numpy().astype(np.complex128)
+    ctx.free()
+    assert np.allclose(pw, np.sum(np.abs(Pg) ** 2, axis=(1, 2)), rtol=1e-6, atol=0)
+    _, P_o, _, _ = oracle.iterate(c["psi"].astype(np.complex128), c["P"].astype(np.complex128),
+                                  c["O"].astype(np.complex128), c["pos"],
+                                  c["I"].astype(np.float64), c["beta"])
+    ref = np.sum(np.abs(P_o) ** 2, axis=(1, 2))
+    say(f"  shares {pw / pw.sum()}  max rel {np.max(np.abs(pw - ref) / ref):.1e}")
+    assert np.allclose(pw, ref, rtol=2e-5, atol=0)
+
+
 MIXED = [
     # (seed, N, F, M, H, W, perturb): the paper's frame edges 188 = 4 x 47 and
     # 200 = 8 x 25.  One mode: 16-column blocks, the last one partial; F =

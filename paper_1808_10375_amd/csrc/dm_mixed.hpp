@@ -270,6 +270,20 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
   }
 }
 
+// Slot (view * nblk + column block) of block b when every column block of a
+// view runs on one XCD: the dispatcher sends block b to XCD b % 8, so XCD x
+// takes the views v = x, x + 8, ... whole, one after the other.  A row of an
+// F = 188 or 200 frame is not a multiple of 128 bytes, so column strips of
+// one view share cache lines across their edges; on one XCD those lines are
+// fetched into its L2 once.  Bijective on whole groups of 8 views; the
+// remaining blocks keep their index.
+__device__ __forceinline__ int xcd_view_slot(int b, int n, int nblk) {
+  const int full = (n / (8 * nblk)) * (8 * nblk);
+  if (b >= full) return b;
+  const int x = b & 7, i = b >> 3;
+  return (8 * (i / nblk) + x) * nblk + i % nblk;
+}
+
 // (2) DFT along CB columns of every mode of one view, the mode sum, the
 // modulus scale and the inverse DFT along the columns, in place in the
 // spectrum buffer.  Thread (c, tl, m) with c fastest.  All LDS is dynamic,
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
   extern __shared__ __align__(16) float2 dyn[];
   const int t = threadIdx.x;
   const int nblk = (F + CB - 1) / CB;
-  const int slot = xcd_group_slot(blockIdx.x, gridDim.x);
+  const int slot = xcd_view_slot(blockIdx.x, gridDim.x, nblk);
   const int2 vm = vmap[slot / nblk];
   const ScanDev& sc = scans[vm.x];
   const int j = uni(vm.y);

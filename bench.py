@@ -288,6 +288,9 @@ def main():
     ap.add_argument("--paper-frame", action="store_true",
                     help="the fly scan at the paper's own frame size instead: 10000 views x "
                          "4 modes x 188^2 frames (mixed-radix transforms)")
+    ap.add_argument("--paper-weak", action="store_true",
+                    help="the per-node shape of the paper's weak scaling instead: 5041 views "
+                         "x 1 mode x 200^2 frames (mixed-radix transforms)")
     ap.add_argument("--conv-iters", type=int, default=100,
                     help="total iterations from the cold start for the err curve")
     ap.add_argument("--cpu-sample", type=int, default=300)
@@ -326,7 +329,12 @@ def main():
     dev = torch.device("cuda:0")
 
     t0 = time.time()
-    if args.paper_frame:
+    if args.paper_weak:
+        scan = synth.weak_scaling_200(4)
+        workload = ("weak-scaling shape of the paper, one node's share: 71x71 raster (5041 "
+                    "views) x 1 mode, 200x200 frames, 1000x1000 object, zone-plate probe, "
+                    "Poisson 1e6 photons/frame")
+    elif args.paper_frame:
         scan = synth.flyscan_raster_188(3)
         workload = ("fly scan at the paper's frame size: 10000 views x 4 modes, 188x188 frames, "
                     "100x100 raster, 1280x1280 object, 8-position motion blur, "
@@ -428,7 +436,7 @@ def main():
                            "alg_flops_per_launch": flops, "avg_launch_ms": views_ms}
         out["dtype"] = "bf16x3/f32"
     if (not args.no_forms and args.config == 1 and not args.paper_frame
-            and args.precision == "fp32"):
+            and not args.paper_weak and args.precision == "fp32"):
         out["forms"] = {"psi_error_last": bench_psi_error_last(scan, args.steps, args.warmup),
                         "probe_first": bench_probe_first(scan, args.steps, args.warmup),
                         "batched": bench_batched(args.steps, args.warmup, args.conv_iters),

@@ -373,14 +373,17 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
 
 // (3) inverse DFT along rows, psi' = psi + beta (Z' - P O), the view's
 // object numerator sum_m conj(P_m) psi'_m and the eps_psi partial sums; all
-// modes of RB rows per block.
+// modes of RB rows per block.  The line buffers alternate between modes, so
+// a mode's spectrum rows go from global memory straight into the buffer the
+// previous mode did not use (its last readers passed the barriers of that
+// mode).
 template <int F>
 __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
     const float2* __restrict__ tw, int M) {
   using C = Mix<F>;
   constexpr int R = C::R, Q = C::Q, QT = C::QT, RB = C::RB, LS = C::LS, NT = C::NT, FF = F * F;
-  __shared__ __align__(16) float2 xb[RB * LS];
+  __shared__ __align__(16) float2 xb[2 * RB * LS];
   __shared__ float2 twl[F];
   __shared__ float2 twq[Q];
   __shared__ float red[2 * (NT / 64)];
@@ -392,7 +395,6 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
   const int row = blockIdx.y * RB + rl;
   const bool active = rl < RB && row < F;
   const bool owner = active && tl < Q;  // holds pixels Q n1 + tl of the row
-  float2* line = xb + rl * LS;
   const int W = uni(sc.W);
   const float beta = sc.beta;
   const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
@@ -404,19 +406,14 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
   float e_d = 0.f, e_n = 0.f;
   for (int m = 0; m < M; ++m) {
     const size_t base = ((size_t)j * M + m) * FF + (size_t)row * F;
-    float4 x[R / 2] = {};
+    float2* line = xb + (m & 1) * (RB * LS) + rl * LS;
     if (owner) {
       const float4* __restrict__ Tr = reinterpret_cast<const float4*>(sc.tspec + base + R * tl);
-#pragma unroll
-      for (int h = 0; h < R / 2; ++h) x[h] = Tr[h];
-    }
-    __syncthreads();  // the previous mode's reads of the line buffer (and the tables)
-    if (owner) {
       float4* d = reinterpret_cast<float4*>(line + R * tl);
 #pragma unroll
-      for (int h = 0; h < R / 2; ++h) d[h] = x[h];
+      for (int h = 0; h < R / 2; ++h) d[h] = Tr[h];
     }
-    __syncthreads();
+    __syncthreads();  // the rows (and, in the first mode, the tables)
     float2 a[R] = {};
     mix_inverse<F>(a, line, twl, twq, tl, active);  // a[n1] = Z' at column Q n1 + tl
     if (owner) {

@@ -23,6 +23,8 @@ Workload shapes follow the paper's cases, restated as synthetic scans:
             incoherent illumination)
   flyscan_raster_188      the paper's frame size: 188x188 frames, 100x100 raster, 1280x1280
             object, 8 sub-positions of motion blur, 1e6 photons/frame, 4 modes
+  weak_scaling_200        the per-node shape of the paper's weak scaling: 200x200 frames,
+            71x71 raster (5041 points), 1000x1000 object, zone-plate probe, single mode
   uneven_spirals_128      16 scans of 200-3000 frames, 3 modes, 128x128 frames, 1024^2 objects
 The paper measured real beamline data that is not available; these seeded
 scans stand in for it.
@@ -373,6 +375,46 @@ def flyscan_raster_188(seed: int = 3, n_frames: int = 10000, n_modes: int = 4,
                         r[3], env, weights, (obj, obj))
     return Scan(I, pos, P0, O0, 0.8, probes.astype(np.complex64),
                 O.astype(np.complex64), "flyscan_raster_188")
+
+
+def zone_plate_probe(f: int, r_in: float, r_out: float, defocus: float) -> np.ndarray:
+    """Probe behind a zone plate with a central stop: an annular pupil
+    r_in <= |k| / (F/2) <= r_out with a defocus phase defocus * (|k| / (F/2))^2
+    rad, propagated to the sample plane by an inverse FFT and centred in the
+    frame; unit L2 norm."""
+    ky = np.fft.fftfreq(f)[:, None] * 2.0
+    kx = np.fft.fftfreq(f)[None, :] * 2.0
+    r = np.sqrt(ky * ky + kx * kx)
+    pupil = ((r >= r_in) & (r <= r_out)).astype(np.complex128)
+    pupil *= np.exp(1j * defocus * r * r)
+    p = np.fft.fftshift(np.fft.ifft2(pupil))
+    return p / np.linalg.norm(p)
+
+
+def weak_scaling_200(seed: int = 4, side: int = 71, obj: int = 1000) -> Scan:
+    """The per-node shape of the paper's weak-scaling runs (Section IV:
+    synthesized single-mode data, 200x200 diffraction patterns through a
+    zone plate, about 5000 points per node): 200x200 frames, a side x side
+    raster (71 x 71 = 5041 points, step 10 px, centred), obj x obj object
+    (amplitude and phase from two independent random fields), zone-plate
+    probe (annular pupil 0.1..0.6 of the detector half-width, defocus 60 rad
+    at its edge: an RMS spot radius of 18 px against the 10 px step),
+    Poisson 1e6 photons/frame, single-mode reconstruction from a Gaussian
+    cold start."""
+    r = streams(seed)
+    f = 200
+    O = grf_object(obj, obj, r[0], r[1])
+    P = zone_plate_probe(f, 0.1, 0.6, 60.0)[None]
+    origin = (obj - f - 10.0 * (side - 1)) / 2.0
+    pos = raster_positions(side, side, 10.0, origin)
+    I_exact = far_field_intensity(P, O, pos, chunk=128)
+    I, _ = poisson_counts(I_exact, 1e6, r[2])
+    y, x = _centred_grid(f)
+    env = np.exp(-(x * x + y * y) / (2.0 * 18.0 ** 2))
+    P0, O0 = cold_start(f, 1, float(np.mean(np.sum(I, axis=(1, 2)))), r[3], env, [1.0],
+                        (obj, obj))
+    return Scan(I, pos, P0, O0, 0.8, P.astype(np.complex64), O.astype(np.complex64),
+                "weak_scaling_200")
 
 
 def uneven_scan_sizes(seed: int = 1000, n_scans: int = 16, lo: int = 200,

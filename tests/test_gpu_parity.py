@@ -372,6 +372,24 @@ def test_flyscan_188_strip_three_iterations():
     check_errors(e_g, e_o)
 
 
+def test_weak_scaling_200_strip_one_step_after_five_iterations():
+    """The paper's weak-scaling shape (200x200 frames, one mode, zone-plate
+    probe) on 40 views of its raster.  Single mode from the flat-phase
+    Gaussian cold start leaves most of the detector below FP32 resolution
+    in the first steps (as for the single-mode raster), so the step is taken
+    from the oracle's state after five iterations."""
+    s = synth.weak_scaling_200(4)
+    n = 40
+    pos, I = s.pos[:n], s.I[:n].astype(np.float64)
+    say("case weak-scaling strip of 40 views, F=200, M=1, one step after 5 oracle iterations")
+    psi, P, O = (oracle.init_views(s.P0, s.O0, pos), s.P0.astype(np.complex128),
+                 s.O0.astype(np.complex128))
+    for _ in range(5):
+        psi, P, O, _ = oracle.iterate(psi, P, O, pos, I, s.beta)
+    one_step_case(dict(psi=psi.astype(np.complex64), P=P.astype(np.complex64),
+                       O=O.astype(np.complex64), I=s.I[:n], pos=pos, beta=s.beta))
+
+
 @pytest.mark.parametrize("view_path", [4, 5])
 @pytest.mark.parametrize("seed,n,f,m,h,w", [(41, 29, 32, 2, 96, 90), (42, 21, 64, 3, 180, 150),
                                             (43, 13, 128, 5, 260, 250)])

@@ -1,6 +1,7 @@
 """Benchmark: multi-mode difference-map iterations on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1|2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 0|1|2]
+                    [--paper-frame | --paper-weak]
 
 A step is one full DM iteration (Eq. 3 view update with the modulus
 projection, Eq. 5 object update, Eq. 4 probe update, Eq. 6 errors) over the
@@ -284,7 +285,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2])
     ap.add_argument("--paper-frame", action="store_true",
                     help="the fly scan at the paper's own frame size instead: 10000 views x "
                          "4 modes x 188^2 frames (mixed-radix transforms)")
@@ -339,6 +340,10 @@ def main():
         workload = ("fly scan at the paper's frame size: 10000 views x 4 modes, 188x188 frames, "
                     "100x100 raster, 1280x1280 object, 8-position motion blur, "
                     "Poisson 1e6 photons/frame")
+    elif args.config == 0:
+        scan = synth.single_mode_raster_32(0)
+        workload = ("single-mode raster: 100 views x 1 mode, 32x32 frames, 10x10 jittered "
+                    "raster, 128x128 object, noise-free")
     elif args.config == 1:
         scan = synth.multimode_spiral_128(1)
         workload = ("multi-mode spiral: 2500 views x 5 Hermite-Gaussian modes, 128x128 frames, "

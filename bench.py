@@ -27,15 +27,18 @@ if ROOT not in sys.path:
 METRIC = ("DM frame·mode/s per iter (plain vs BF16-split/warm-start), "
           "iters to err≤1e-3")
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1808_10375_amd/csrc/dm_kernels.hpp",
-                  "paper_1808_10375_amd/csrc/dm_fft.hpp"]
+CSRC = os.path.join(ROOT, "paper_1808_10375_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_views_2500x5_128.json")
+ORACLE_ERR_FILE = os.path.join(ROOT, "tests", "golden", "spiral_2500_err.json")
 
 
 def kernel_hash() -> str:
+    """Hash of every library source (kernels and the launch code that picks
+    their shapes): a committed traffic figure is used only while it matches."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -79,36 +82,103 @@ def step_alg_bytes(n, m, f):
     return n * m * 24 * f * f + n * 4 * f * f
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Cores this process may run on, capped at the 16 a one-GPU share of the
+    box provides."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_iteration(oracle, psi, P, O, pos, I, beta, pool, chunk=32):
+    """One oracle iteration in its default order (views, object, probe).
+    With a thread pool the view update of disjoint chunks of views runs on
+    the pool (views are independent; numpy's transforms release the
+    interpreter lock); the object and probe updates run as written."""
+    if pool is None:
+        psi_new = oracle.view_update(psi, P, O, pos, I, beta)
+    else:
+        sl = [slice(a, a + chunk) for a in range(0, len(pos), chunk)]
+        psi_new = np.concatenate(list(pool.map(
+            lambda s: oracle.view_update(psi[s], P, O, pos[s], I[s], beta), sl)))
+    O_new, _ = oracle.object_update(psi_new, P, O, pos)
+    P_new, _ = oracle.probe_update(psi_new, O_new, P, pos)
+    return psi_new, P_new, O_new
+
+
 def cpu_baseline(scan, n_sample: int, reps: int = 3):
-    """The FP64 oracle, single-threaded, on the first n_sample views of the
-    same scan (same frame size, modes and object)."""
+    """The FP64 oracle on the first n_sample views of the same scan (same
+    frame size, modes and object), timed on one thread and on every host
+    core; the line reports the all-core figure and keeps the one-thread one
+    beside it."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from oracle import dm_oracle as oracle
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        limiter = threadpool_limits(1)   # numpy's own BLAS threads stay at 1
     except Exception:  # pragma: no cover
         limiter = None
     pos = scan.pos[:n_sample]
     I = scan.I[:n_sample].astype(np.float64)
-    psi = oracle.init_views(scan.P0, scan.O0, pos)
-    P = scan.P0.astype(np.complex128)
-    O = scan.O0.astype(np.complex128)
-    psi, P, O, _ = oracle.iterate(psi, P, O, pos, I, scan.beta)  # warm-up
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        psi, P, O, _ = oracle.iterate(psi, P, O, pos, I, scan.beta)
-        times.append(time.perf_counter() - t0)
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    t = float(np.median(times))
     m = scan.P0.shape[0]
-    return {"value": n_sample * m / t, "unit": "frame·mode/s", "cores": 1,
+    cores = host_cores()
+    res = {}
+    for n_thr in (1, cores):
+        psi = oracle.init_views(scan.P0, scan.O0, pos)
+        P = scan.P0.astype(np.complex128)
+        O = scan.O0.astype(np.complex128)
+        pool = ThreadPoolExecutor(n_thr) if n_thr > 1 else None
+        psi, P, O = _oracle_iteration(oracle, psi, P, O, pos, I, scan.beta, pool)  # warm-up
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            psi, P, O = _oracle_iteration(oracle, psi, P, O, pos, I, scan.beta, pool)
+            times.append(time.perf_counter() - t0)
+        if pool is not None:
+            pool.shutdown()
+        res[n_thr] = float(np.median(times))
+    if limiter is not None and hasattr(limiter, "unregister"):
+        limiter.unregister()
+    t1, tn = res[1], res[cores]
+    sample = (f"first {n_sample} of {scan.n_frames} views (M={m}, F={scan.frame}, "
+              f"object {scan.obj_shape[0]}x{scan.obj_shape[1]}), median of {reps} iterations "
+              f"after 1 warm-up, FP64 numpy")
+    return {"value": n_sample * m / tn, "unit": "frame·mode/s", "cores": cores,
             "kind": "oracle",
-            "sample": (f"first {n_sample} of {scan.n_frames} views (M={m}, F={scan.frame}, "
-                       f"object {scan.obj_shape[0]}x{scan.obj_shape[1]}), median of {reps} "
-                       f"iterations after 1 warm-up, FP64 numpy, 1 thread; "
-                       f"{t:.2f} s per iteration")}
+            "sample": (f"{sample}; view update over {cores} threads (chunks of views), object "
+                       f"and probe updates on one; {tn:.2f} s per iteration"),
+            "cpu_model": host_cpu_model(),
+            "single_thread": {"value": n_sample * m / t1, "cores": 1,
+                              "s_per_iteration": t1}}
+
+
+def oracle_final_err():
+    """The FP64 oracle's err after 100 iterations of the 2500-view spiral scan
+    (written by tests/golden/make_spiral_2500_err.py), or None."""
+    try:
+        with open(ORACLE_ERR_FILE) as fh:
+            return float(json.load(fh)["eps_probe"][-1])
+    except (OSError, ValueError, KeyError, IndexError):
+        return None
+
+
+def iters_to(errs, thr):
+    """First iteration t >= 1 with err_t <= thr, or None."""
+    return next((i + 1 for i, e in enumerate(errs) if e <= thr), None)
 
 
 COPY_BYTES = 1 << 30
@@ -176,47 +246,33 @@ def bench_batched(steps: int, warmup: int, conv_iters: int):
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def bench_bf16x3(scan, steps: int, warmup: int, conv_iters: int, fp32_err):
+def bench_bf16x3(scan, steps: int, warmup: int, conv_iters: int, fp32_err, oracle_err=None):
     """The same scan through the BF16x3 form (each 2-D DFT as split-bfloat16
     complex matrix products on MFMA); 96 F^3 flops per frame-mode."""
-    import torch
     from paper_1808_10375_amd import dm
-    dev = torch.device("cuda:0")
     n, f, m = scan.n_frames, scan.frame, scan.n_modes
-    stream = torch.cuda.Stream(device=dev)
-    with torch.cuda.stream(stream):
-        ctx = dm.DMContext(torch.from_numpy(scan.I).to(dev), scan.pos,
-                           torch.from_numpy(scan.P0).to(dev), torch.from_numpy(scan.O0).to(dev),
-                           beta=scan.beta, precision=dm.DM_BF16X3_DFT,
-                           flags=dm.DM_FLAG_PHASE_TIMING, stream=stream)
-        ctx.iterate(warmup)
-        ctx.phase_times()
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        ctx.iterate(steps)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        phases, n_timed = ctx.phase_times()
-        done = warmup + steps
-        if conv_iters > done:
-            ctx.iterate(conv_iters - done)
-        hist = ctx.error_history(1, max(conv_iters, done))
-        ctx.free()
+    r = run_scan(scan, steps, warmup, conv_iters, 0, dm.DM_BF16X3_DFT)
+    phases, n_timed = r["phases"], r["n_timed"]
     views_ms = phases["views"] / max(n_timed, 1)
+    ms = 1e3 * r["elapsed"] / steps
     flops = 96.0 * f ** 3 * n * m
-    errs = [e["eps_probe"] for e in hist]
-    return {"workload": "the same scan as the headline line",
-            "value": n * m / (elapsed / steps), "unit": "frame·mode/s",
-            "ms_per_step": 1e3 * elapsed / steps, "views_ms": views_ms,
-            "roofline": {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
-                         "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": flops / (views_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
-                         "kernel": "views (k_mf_rows_fwd, k_mf_cols, k_mf_rows_inv)",
-                         "alg_flops_per_launch": flops},
-            "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
-            "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
-            "final_err_vs_fp32": {"bf16x3": errs[-1], "fp32": fp32_err}}
+    errs = [e["eps_probe"] for e in r["hist"]]
+    out = {"workload": "the same scan as the headline line",
+           "value": n * m / (ms * 1e-3), "unit": "frame·mode/s",
+           "ms_per_step": ms, "views_ms": views_ms,
+           "roofline": {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
+                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": flops / (views_ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS,
+                        "kernel": "views (k_mf_rows_fwd, k_mf_cols, k_mf_rows_inv)",
+                        "alg_flops_per_launch": flops},
+           "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
+           "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
+           "final_err_vs_fp32": {"bf16x3": errs[-1], "fp32": fp32_err}}
+    if oracle_err is not None and len(errs) >= 100:
+        it = iters_to(errs, 1.1 * oracle_err)
+        out["iters_to_err_threshold"] = {"threshold": 1.1 * oracle_err, "iters": it,
+                                         "seconds": None if it is None else it * ms * 1e-3}
+    return out
 
 
 def bench_psi_error_last(scan, steps: int, warmup: int):
@@ -278,6 +334,78 @@ def bench_probe_first(scan, steps: int, warmup: int):
             "ms_per_step": 1e3 * elapsed / steps,
             "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
             "err_after": {"iterations": warmup + steps, "eps_probe": err}}
+
+
+def run_scan(scan, steps: int, warmup: int, conv_iters: int, flags: int = 0,
+             precision: int = 0, view_path=None):
+    """Warm-up, then `steps` timed iterations of one scan (inputs already in
+    HBM, torch.cuda.synchronize() on both sides), the phase times of the
+    timed iterations, and the err curve of conv_iters iterations from the
+    cold start."""
+    import torch
+    from paper_1808_10375_amd import dm
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        I = torch.from_numpy(scan.I).to(dev)
+        P0 = torch.from_numpy(scan.P0).to(dev)
+        O0 = torch.from_numpy(scan.O0).to(dev)
+        ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta,
+                           flags=flags | dm.DM_FLAG_PHASE_TIMING, stream=stream,
+                           precision=precision)
+        if view_path is not None:
+            tune = ctx.tuning()
+            ctx.set_tuning(tune["obj_tile"], tune["probe_chunks"], view_path)
+        vp = ctx.tuning()["view_path"]
+        ctx.iterate(warmup)
+        ctx.phase_times()  # drop the warm-up marks (synchronises)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        ctx.iterate(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        phases, n_timed = ctx.phase_times()
+        done = warmup + steps
+        if conv_iters > done:
+            ctx.iterate(conv_iters - done)
+        hist = ctx.error_history(1, max(conv_iters, done))
+        ctx.free()
+        del I, P0, O0
+    return {"elapsed": elapsed, "phases": phases, "n_timed": n_timed, "hist": hist,
+            "view_path": vp}
+
+
+def view_roofline(n, m, f, r, psi_error_last=False, traffic=None):
+    """HBM roofline of the view update (the dominant phase): its algorithmic
+    bytes over its live-measured average duration."""
+    views_ms = r["phases"]["views"] / max(r["n_timed"], 1)
+    alg = views_alg_bytes(n, m, f)
+    achieved = alg / (views_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": (view_kernel_name(r["view_path"], f, psi_error_last)
+                       if r["view_path"] != 1 else "views (3 kernels)"),
+            "alg_bytes_per_launch": alg, "avg_launch_ms": views_ms}
+
+
+def bench_flyscan_256(steps: int, warmup: int):
+    """The largest single-GPU workload beside the headline: 10000 views x 8
+    modes x 256^2 frames (spectra through the three-kernel path)."""
+    from paper_1808_10375_amd import synth
+    t0 = time.time()
+    scan = synth.flyscan_raster_256(2)
+    print(f"# generated {scan.name} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    n, f, m = scan.n_frames, scan.frame, scan.n_modes
+    r = run_scan(scan, steps, warmup, 0)
+    ms = 1e3 * r["elapsed"] / steps
+    return {"workload": ("fly scan: 10000 views x 8 modes, 256x256 frames, 100x100 raster, "
+                         "3072x3072 object, 8-position motion blur, Poisson 1e6 photons/frame"),
+            "value": n * m / (ms * 1e-3), "unit": "frame·mode/s", "ms_per_step": ms,
+            "steps": steps, "warmup": warmup,
+            "roofline": view_roofline(n, m, f, r),
+            "step_roofline_frac": step_alg_bytes(n, m, f) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "phase_ms_per_iter": {k: v / max(r["n_timed"], 1) for k, v in r["phases"].items()}}
 
 
 def main():
@@ -356,44 +484,19 @@ def main():
 
     n, f, m = scan.n_frames, scan.frame, scan.n_modes
     h, w = scan.obj_shape
-    stream = torch.cuda.Stream(device=dev)
-    with torch.cuda.stream(stream):
-        I = torch.from_numpy(scan.I).to(dev)
-        P0 = torch.from_numpy(scan.P0).to(dev)
-        O0 = torch.from_numpy(scan.O0).to(dev)
-        flags = (dm.DM_FLAG_PHASE_TIMING | (dm.DM_FLAG_MULTIPASS if args.multipass else 0)
-                 | (dm.DM_FLAG_PSI_ERROR_LAST if args.psi_error_last else 0))
-        prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
-        ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta, flags=flags, stream=stream,
-                           precision=prec)
-        if args.view_path is not None:
-            tune = ctx.tuning()
-            ctx.set_tuning(tune["obj_tile"], tune["probe_chunks"], args.view_path)
-        view_path = ctx.tuning()["view_path"]
-        ctx.iterate(args.warmup)
-        ctx.phase_times()  # drop the warm-up marks (synchronises)
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        ctx.iterate(args.steps)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        phases, n_timed = ctx.phase_times()
-        done = args.warmup + args.steps
-        if args.conv_iters > done:
-            ctx.iterate(args.conv_iters - done)
-        hist = ctx.error_history(1, max(args.conv_iters, done))
-        ctx.free()
+    flags = ((dm.DM_FLAG_MULTIPASS if args.multipass else 0)
+             | (dm.DM_FLAG_PSI_ERROR_LAST if args.psi_error_last else 0))
+    prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
+    r = run_scan(scan, args.steps, args.warmup, args.conv_iters, flags, prec, args.view_path)
+    elapsed, phases, n_timed, hist = r["elapsed"], r["phases"], r["n_timed"], r["hist"]
+    view_path = r["view_path"]
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * m / (elapsed / args.steps)
-    views_ms = phases["views"] / max(n_timed, 1)
-    alg = views_alg_bytes(n, m, f)
-    achieved = alg / (views_ms * 1e-3) / 1e9
     key = f"n{n}_m{m}_f{f}_o{h}x{w}"
     traffic = measured_traffic(key, view_kernel_name(view_path, f, args.psi_error_last))
     errs = [e["eps_probe"] for e in hist]
-    reach = next((i + 1 for i, e in enumerate(errs) if e <= 1e-3), None)
+    reach = iters_to(errs, 1e-3)
 
     out = {
         "metric": METRIC,
@@ -404,7 +507,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": "strong",
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
@@ -412,19 +515,26 @@ def main():
                    "object": [h, w], "beta": scan.beta,
                    "precision": (args.precision + ("-fft" if args.precision == "fp32" else "-dft")
                                  + ("-multipass" if args.multipass else ""))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": (view_kernel_name(view_path, f, args.psi_error_last)
-                                if view_path != 1
-                                else "views (3 kernels)"),
-                     "alg_bytes_per_launch": alg, "avg_launch_ms": views_ms},
+        "roofline": view_roofline(n, m, f, r, args.psi_error_last, traffic),
         "step_roofline_frac": step_alg_bytes(n, m, f) / (ms_per_step * 1e-3) / 1e9
         / HBM_PEAK_GBS,
         "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
         "iters_to_err_1e-3": reach,
         "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
     }
+    # where err <= 1e-3 is not reached (Poisson data has no consistent fixed
+    # point), iterations are counted to 1.1 x the FP64 oracle's final err on
+    # the same scan
+    ofe = oracle_final_err() if (args.config == 1 and not args.paper_frame
+                                 and not args.paper_weak) else None
+    if reach is None and ofe is not None and len(errs) >= 100:
+        thr = 1.1 * ofe
+        it = iters_to(errs, thr)
+        out["iters_to_err_threshold"] = {
+            "threshold": thr, "oracle_final_err": ofe, "iters": it,
+            "seconds": None if it is None else it * ms_per_step * 1e-3,
+            "rule": "err <= 1e-3 not reached; first iteration with err <= 1.1 x the FP64 "
+                    "oracle's err after 100 iterations of this scan"}
     if args.paper_frame:
         # context only: the paper's measured rate on its 10000-frame 188^2
         # scan (FP64, four V100s, 50 iterations in 25.69 s; mode count not
@@ -433,6 +543,7 @@ def main():
         out["paper_context"] = {"views_per_s": 10000 * 50 / 25.69,
                                 "hardware": "4x V100, FP64", "comparable": False}
     if args.precision == "bf16x3":
+        views_ms = out["roofline"]["avg_launch_ms"]
         flops = 96.0 * f ** 3 * n * m
         out["roofline"] = {"bound": "mfma", "achieved": flops / (views_ms * 1e-3) / 1e12,
                            "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -446,7 +557,14 @@ def main():
                         "probe_first": bench_probe_first(scan, args.steps, args.warmup),
                         "batched": bench_batched(args.steps, args.warmup, args.conv_iters),
                         "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,
-                                               errs[-1])}
+                                               errs[-1], ofe)}
+        b3 = out["forms"]["bf16x3"].get("iters_to_err_threshold")
+        a = out.get("iters_to_err_threshold")
+        if a and b3 and a["seconds"] and b3["seconds"]:
+            # speedup of the form over the plain FP32 path at equal final error
+            out["forms"]["bf16x3"]["speedup_at_equal_err"] = a["seconds"] / b3["seconds"]
+        # the largest single-GPU workload, measured by the default run too
+        out["other_configs"] = {"fly_scan_256": bench_flyscan_256(5, 2)}
     if not args.no_cpu:
         print("# timing the FP64 oracle on a sample of the scan", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scan, min(args.cpu_sample, n))

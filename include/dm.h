@@ -61,8 +61,9 @@ typedef enum {
   DM_OK = 0,
   DM_E_ARG = -1,          /* bad descriptor value, null/misaligned pointer,
                              non-finite intensity                          */
-  DM_E_UNSUPPORTED = -2,  /* valid in the paper but not built: F not a power
-                             of two in [16, 256], M > 16, unknown precision */
+  DM_E_UNSUPPORTED = -2,  /* valid in the paper but not built: F neither a
+                             power of two in [16, 256] nor 188 or 200,
+                             M > 16, unknown precision                     */
   DM_E_BOUNDS = -3,       /* a window leaves the object                     */
   DM_E_WORKSPACE = -4,    /* workspace smaller than dm_workspace_bytes()    */
   DM_E_HIP = -5,          /* HIP runtime error (context becomes failed)     */

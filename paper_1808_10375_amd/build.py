@@ -15,10 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdm.so")
 
+# translation units; every other file under csrc/ and include/ is a header
+# they include
 SOURCES = ["dm_api.hip", "dmnet_api.hip"]
-HEADERS = ["dm_fft.hpp", "dm_kernels.hpp", "dmnet_kernels.hpp",
-           os.path.join("..", "..", "include", "dm.h"),
-           os.path.join("..", "..", "include", "dmnet.h")]
 
 # Packed FP32 instructions are kept out of every kernel.
 HIPCC_FLAGS = [

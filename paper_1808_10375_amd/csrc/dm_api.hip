@@ -220,7 +220,9 @@ CtxLayout ctx_layout(int n_scans, const dm_desc* d) {
                ? take((size_t)stream_slots(n_scans, d) * d[0].frame * d[0].frame *
                       (8 * (size_t)d[0].n_modes + 4))
                : 0;
-  C.flags = take(sizeof(int));
+  // [0]: bit 2 = non-finite intensities at init; [1 + s]: bit 1 = a
+  // non-finite error norm in scan s since its state was last set
+  C.flags = take(sizeof(int) * (1 + (size_t)n_scans));
   C.header = off;
   for (int s = 0; s < n_scans; ++s) {
     C.sl.push_back(scan_layout(d[s]));
@@ -317,6 +319,9 @@ struct dm_ctx {
   bool failed = false;
   std::string err;
   int iters = 0;
+  // iterations up to this one were not run by this context since its state
+  // was last set (dm_set_state): their error records are not valid
+  int first_iter = 0;
   int total_views = 0, total_tiles = 0, total_chunks = 0;
   int stream_slots = 0;
   dm_tuning tune{};
@@ -352,6 +357,7 @@ struct dm_ctx {
   const uint4* wf() { return at<uint4>(CL.wf); }
   bool bf16x3() const { return is_bf16x3(scans[0].d); }
   int* flags_dev() { return at<int>(CL.flags); }
+  int n_flags() const { return 1 + (int)scans.size(); }
 };
 
 namespace {
@@ -975,7 +981,8 @@ dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const floa
   }
   INIT_HIP(hipMemcpyAsync(c->vmap(), vmap.data(), vmap.size() * sizeof(int2),
                           hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(), 1, 0);
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(),
+                     c->n_flags(), 0);
   INIT_HIP(hipGetLastError());
   for (int s = 0; s < n_scans; ++s) {
     auto& S = c->scans[s];
@@ -1012,8 +1019,8 @@ dm_status read_errors(dm_ctx* c, int s, int first, int count, dm_errors* out) {
                              c->stream));
   }
   int flags_host = 0;
-  DM_HIP(c, hipMemcpyAsync(&flags_host, c->flags_dev(), sizeof(int), hipMemcpyDeviceToHost,
-                           c->stream));
+  DM_HIP(c, hipMemcpyAsync(&flags_host, c->flags_dev() + 1 + s, sizeof(int),
+                           hipMemcpyDeviceToHost, c->stream));
   DM_HIP(c, hipStreamSynchronize(c->stream));
   std::memcpy(out, tmp.data(), sizeof(dm_errors) * count);
   if (flags_host & 1) {
@@ -1282,8 +1289,9 @@ dm_status dm_scan_error_history(dm_ctx* c, int32_t scan, int32_t first, int32_t 
   if (s != DM_OK) return s;
   if (!out || count < 0) { c->err = "bad arguments"; return DM_E_ARG; }
   if (count == 0) return DM_OK;
-  if (first < 1 || first + count - 1 > c->iters || c->iters - first + 1 > dmk::kRing) {
-    c->err = "requested iterations are not in the error ring";
+  if (first <= c->first_iter || first + count - 1 > c->iters ||
+      c->iters - first + 1 > dmk::kRing) {
+    c->err = "requested iterations are not in the error ring (or precede the last dm_set_state)";
     return DM_E_ARG;
   }
   return read_errors(c, scan, first, count, out);
@@ -1293,8 +1301,10 @@ dm_status dm_error(dm_ctx* c, dm_errors* out) {
   dm_status s = check_ctx(c);
   if (s != DM_OK) return s;
   if (!out) { c->err = "out is NULL"; return DM_E_ARG; }
-  if (c->iters == 0) {
+  if (c->iters == c->first_iter) {
+    // no iteration since the start or the last dm_set_state
     std::memset(out, 0, sizeof *out);
+    out->iter = c->iters;
     return DM_OK;
   }
   return read_errors(c, 0, c->iters, 1, out);
@@ -1361,7 +1371,12 @@ dm_status dm_set_state(dm_ctx* c, const void* psi_src, const void* probe_src,
   hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream,
                      c->sat<int>(0, S.L.counter), 1, iter);
   DM_LAUNCHED(c, "k_fill_int");
+  // a restored state starts a new run: its numeric flag is clear and the
+  // error records of earlier iterations are no longer this run's
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev() + 1, 1, 0);
+  DM_LAUNCHED(c, "k_fill_int");
   c->iters = iter;
+  c->first_iter = iter;
   return DM_OK;
 }
 
@@ -1447,10 +1462,12 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   DM_TRY(apply_tuning(c, best));
   // rebuild the initial state and forget the timed iterations
   for (int sidx = 0; sidx < (int)c->scans.size(); ++sidx) DM_TRY(init_scan_state(c, sidx));
-  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(), 1, 0);
+  hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flags_dev(),
+                     c->n_flags(), 0);
   DM_LAUNCHED(c, "k_fill_int");
   DM_HIP(c, hipStreamSynchronize(c->stream));
   c->iters = 0;
+  c->first_iter = 0;
   for (auto& m : c->marks) { c->event_pool.push_back(m.a); c->event_pool.push_back(m.b); }
   c->marks.clear();
   c->timed_iters = 0;

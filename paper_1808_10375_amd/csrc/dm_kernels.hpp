@@ -1378,7 +1378,7 @@ __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scan
     }
     ring[it % kRing] = e;
     *counter = it + 1;
-    if (bad) atomicOr(flags, 1);
+    if (bad) atomicOr(flags + 1 + blockIdx.x, 1);
   }
 }
 

@@ -109,3 +109,114 @@ def test_patches_reproduce_constants_and_interior_linear_ramps():
     # the clamped border rows repeat the first input row
     assert np.allclose(z.real[0], z.real[0, :] * 0 + (2.0 + 0.0 - 0.25 * np.clip(
         np.arange(2 * s) / 2.0 - 0.25, 0, s - 1)))
+
+
+# ---------------------------------------------------------------------------
+# the bfloat16 rounding hook, pinned by an independent engine: the same
+# network built from torch's CPU convolutions (float64) and differentiated by
+# torch's autograd, with the roundings placed as custom autograd steps.  A
+# rounding missing, misplaced (skip concatenation, second convolution of a
+# level, head input) or applied to the bias gradient moves some values by a
+# bfloat16 ulp (~4e-3 relative) and fails the 1e-10 bar.
+# ---------------------------------------------------------------------------
+def _torch_rounded_network(levels):
+    torch = pytest.importorskip("torch")
+    F = torch.nn.functional
+
+    def bf16(t):
+        # float64 -> float32 -> bfloat16 (nearest even) -> float64
+        return t.float().to(torch.bfloat16).to(torch.float64)
+
+    class RoundInput(torch.autograd.Function):
+        """bfloat16 input of a 3x3 convolution; the gradient passes as is."""
+        @staticmethod
+        def forward(ctx, t):
+            return bf16(t)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class RoundOutputGrad(torch.autograd.Function):
+        """Identity forward; the output gradient entering the convolution's
+        weight and data gradients is rounded to bfloat16."""
+        @staticmethod
+        def forward(ctx, t):
+            return t.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return bf16(g)
+
+    def conv3(x, w, b):
+        y = RoundOutputGrad.apply(F.conv2d(RoundInput.apply(x), w, padding=1))
+        # the bias is added after the rounding step, so its gradient is the
+        # unrounded output gradient
+        return y + b[None, :, None, None]
+
+    def forward(params, x):
+        it = iter(range(0, len(params), 2))
+        h, skips = x, []
+        for l in range(levels):
+            i = next(it)
+            h = torch.relu(conv3(h, params[i], params[i + 1]))
+            i = next(it)
+            h = torch.relu(conv3(h, params[i], params[i + 1]))
+            skips.append(h)
+            if l < levels - 1:
+                h = F.avg_pool2d(h, 2)
+        for l in range(levels - 2, -1, -1):
+            u = torch.cat([F.interpolate(h, scale_factor=2, mode="nearest"), skips[l]], dim=1)
+            i = next(it)
+            h = torch.relu(conv3(u, params[i], params[i + 1]))
+            i = next(it)
+            h = torch.relu(conv3(h, params[i], params[i + 1]))
+        i = next(it)
+        return F.conv2d(h, params[i], params[i + 1])     # 1x1 head, not rounded
+
+    return torch, forward
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_bf16_activation_hook_against_torch_autograd(levels):
+    torch, tforward = _torch_rounded_network(levels)
+    rng = np.random.default_rng(40 + levels)
+    c0, s = 3, 8
+    params = net.init_params(41, c0, levels)
+    params = [p + 0.05 * rng.standard_normal(p.shape) for p in params]
+    x = rng.uniform(0, 1, size=(2, 1, s, s))
+    target = rng.standard_normal((2, 2, s, s))
+    loss, grads, y = net.loss_and_grads(params, x, target, levels, act_round=net.bf16_round)
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in params]
+    ty = tforward(tp, torch.tensor(x))
+    tl = torch.mean((ty - torch.tensor(target)) ** 2)
+    tl.backward()
+    yt = ty.detach().numpy()
+    assert np.max(np.abs(y - yt)) <= 1e-10 * np.max(np.abs(yt))
+    assert abs(loss - tl.item()) <= 1e-12 * abs(loss)
+    for k, (g, t) in enumerate(zip(grads, tp)):
+        gt = t.grad.numpy()
+        assert np.max(np.abs(g - gt)) <= 1e-10 * max(np.max(np.abs(gt)), 1e-30), k
+    # the rounding is not a no-op on this network: without it the output moves
+    y0 = net.forward(params, x, levels)[0]
+    assert np.max(np.abs(y0 - y)) > 1e-4 * np.max(np.abs(y))
+
+
+def test_bf16_hook_is_a_no_op_on_bfloat16_exact_networks():
+    """Integer weights, inputs and biases on one level (no pooling) keep
+    every activation and gradient a small integer (exact in bfloat16):
+    rounded and unrounded runs agree bit for bit, so the hook changes
+    nothing but the rounding."""
+    levels, c0, s = 1, 2, 4
+    rng = np.random.default_rng(7)
+    params = [rng.integers(-1, 2, size=p.shape).astype(np.float64)
+              for p in net.init_params(0, c0, levels)]
+    x = rng.integers(0, 2, size=(1, 1, s, s)).astype(np.float64)
+    y_r, cache_r = net.forward(params, x, levels, act_round=net.bf16_round)
+    y_u, cache_u = net.forward(params, x, levels)
+    assert np.max(np.abs(y_u)) < 128 and np.array_equal(y_r, y_u)
+    dy = rng.integers(-2, 3, size=y_u.shape).astype(np.float64)
+    g_r = net.backward(params, cache_r, dy, levels)
+    g_u = net.backward(params, cache_u, dy, levels)
+    for a, b in zip(g_r, g_u):
+        assert np.max(np.abs(b)) < 256 and np.array_equal(a, b)

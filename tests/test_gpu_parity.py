@@ -321,10 +321,13 @@ def test_mode_power_matches_the_probe_and_the_oracle(seed, n, f, m, h, w):
 
 MIXED = [
     # (seed, N, F, M, H, W, perturb): the paper's frame edges 188 = 4 x 47 and
-    # 200 = 8 x 25.  One mode: 16-column blocks, the last one partial; F =
-    # 188: five-row blocks, the last one with three rows; 16 modes: one or two
-    # columns per block.  Many random modes on few views make the probe
-    # division ill-conditioned, so those cases start near a physical state.
+    # 200 = 8 x 25.  Column blocks of the column kernel (at most 512 threads,
+    # M (Q + 1) threads per column): F = 188 with one mode takes 8 columns, the
+    # last block partial (188 = 23 x 8 + 4); 4 modes at 188 and 8 modes at 200
+    # take 2 columns, 3 modes at 200 take 4, and 16 modes one column.  Row
+    # blocks: five rows at 188, the last one with three rows (188 = 37 x 5 +
+    # 3), nine at 200.  Many random modes on few views make the probe division
+    # ill-conditioned, so those cases start near a physical state.
     (51, 9, 188, 1, 300, 260, None),
     (52, 7, 188, 4, 260, 300, None),
     (53, 6, 200, 3, 280, 320, None),
@@ -365,10 +368,11 @@ def test_flyscan_188_strip_three_iterations():
                                               s.I.astype(np.float64), s.beta)
     den = oracle.object_update(psi_o, P_o, O_o, s.pos)[1]
     psi_g, P_g, O_g, e_g, it = gpu_one_step(psi0, s.P0, s.O0, s.I, s.pos, s.beta, n_iter=3)
-    r = (rel(psi_g, psi_o), rel_weighted(O_g, O_o, den), rel(P_g, P_o))
-    say(f"  rel L2 psi {r[0]:.2e}  O(weighted) {r[1]:.2e}  P {r[2]:.2e}")
+    r = (rel(psi_g, psi_o), rel_weighted(O_g, O_o, den), rel(P_g, P_o), rel(O_g, O_o))
+    say(f"  rel L2 psi {r[0]:.2e}  O(weighted) {r[1]:.2e}  P {r[2]:.2e}  O(plain) {r[3]:.2e}")
     assert it == 3
-    assert max(r) <= TOL, r
+    # the unweighted object bound is 10x looser, as in every one-step case
+    assert max(r[:3]) <= TOL and r[3] <= 10 * TOL, r
     check_errors(e_g, e_o)
 
 
@@ -442,3 +446,41 @@ def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
                 assert abs(e["eps_psi"] - hist_o[k]["eps_psi"]) <= 1e-4 * hist_o[k]["eps_psi"]
     a, b = res[0], res[dm.DM_FLAG_PSI_ERROR_LAST]
     assert rel(a[0], b[0]) <= TOL and rel(a[1], b[1]) <= TOL
+
+
+def test_numeric_flag_and_history_after_restored_state():
+    """A state holding NaN makes the errors non-finite (DM_E_NUMERIC); a
+    finite state restored with dm_set_state starts a new run: the flag is
+    clear, the records before the restore point are refused, dm_error gives
+    zeros until the next iteration, and that iteration's errors equal the
+    oracle's."""
+    torch = _torch()
+    from paper_1808_10375_amd import dm
+    say("case numeric flag cleared by dm_set_state F=32 M=2")
+    c = synth.random_case(33, 9, 32, 2, 90, 80)
+    dev = torch.device("cuda:0")
+    Pt = torch.from_numpy(c["P"]).to(dev)
+    Ot = torch.from_numpy(c["O"]).to(dev)
+    ctx = dm.DMContext(torch.from_numpy(c["I"]).to(dev), c["pos"], Pt, Ot, beta=c["beta"])
+    bad = c["psi"].copy()
+    bad[3, 1, 5, 7] = np.nan
+    ctx.set_state(torch.from_numpy(bad).to(dev), Pt, Ot, 0)
+    ctx.iterate(1)
+    with pytest.raises(dm.DMError) as ex:
+        ctx.errors()
+    assert ex.value.status == dm.DM_E_NUMERIC
+    ctx.set_state(torch.from_numpy(c["psi"]).to(dev), Pt, Ot, 5)
+    e0 = ctx.errors()
+    assert e0["iter"] == 5 and e0["eps_probe"] == 0.0
+    with pytest.raises(dm.DMError) as ex:
+        ctx.error_history(1, 5)
+    assert ex.value.status == dm.DM_E_ARG
+    ctx.iterate(1)
+    e = ctx.errors()
+    hist = ctx.error_history(6, 1)
+    ctx.free()
+    _, _, _, e_o = oracle.iterate(c["psi"].astype(np.complex128), c["P"].astype(np.complex128),
+                                  c["O"].astype(np.complex128), c["pos"],
+                                  c["I"].astype(np.float64), c["beta"])
+    assert e["iter"] == 6 and hist[0]["iter"] == 6
+    check_errors(e, e_o)

@@ -48,7 +48,7 @@ import numpy as np
 __all__ = [
     "dft2", "idft2", "exit_waves", "constrained_ft", "view_update",
     "object_update", "probe_update", "rel_change", "iterate", "init_views",
-    "run",
+    "run", "mode_gram", "orthogonalize_modes",
 ]
 
 
@@ -209,6 +209,43 @@ def iterate(psi, P, O, pos, I, beta, probe_first: bool = False):
                            for k in range(P.shape[0])],
     }
     return psi_new, P_new, O_new, errors
+
+
+# ---------------------------------------------------------------------------
+# orthogonal probe modes (the mixed-state treatment the multi-mode method of
+# Section II builds on; the paper cites it and does not spell it out)
+# ---------------------------------------------------------------------------
+def mode_gram(P) -> np.ndarray:
+    """G[k, l] = sum_r conj(P_k(r)) P_l(r): the overlap (Gram) matrix of the
+    probe modes, M x M Hermitian positive semi-definite."""
+    P = np.asarray(P, dtype=np.complex128)
+    flat = P.reshape(P.shape[0], -1)
+    return np.conj(flat) @ flat.T
+
+
+def orthogonalize_modes(psi, P):
+    """Replace the probe modes by orthogonal ones spanning the same space:
+    with G = V diag(lam) V^H (eigenvalues descending), the new modes are
+    Q_a = sum_k V[k, a] P_k, whose Gram matrix is diag(lam).  The views get
+    the same unitary mix, psi'_{j,a} = sum_k V[k, a] psi_{j,k}, so the
+    iteration continues from an equivalent state: the intensity model
+    sum_k |F[P_k O]|^2 (Eq. 1), the mode sum of F_c, the object update and
+    the probe update are all unchanged by a unitary mix of the modes.
+
+    Each column of V is given a fixed phase: its entry of largest modulus
+    (the first such) is made real and positive.  The eigenvectors come from
+    the library routine numpy.linalg.eigh.
+    Returns (psi', Q, lam, V)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    P = np.asarray(P, dtype=np.complex128)
+    lam, V = np.linalg.eigh(mode_gram(P))
+    lam, V = lam[::-1].copy(), V[:, ::-1].copy()
+    for a in range(V.shape[1]):
+        k = int(np.argmax(np.abs(V[:, a])))
+        V[:, a] *= np.conj(V[k, a]) / abs(V[k, a])
+    Q = np.einsum("ka,kyx->ayx", V, P)
+    psi_new = np.einsum("ka,jkyx->jayx", V, psi)
+    return psi_new, Q, lam, V
 
 
 def init_views(P0, O0, pos) -> np.ndarray:

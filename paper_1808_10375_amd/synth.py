@@ -92,6 +92,14 @@ class Scan:
     def obj_shape(self):
         return tuple(int(s) for s in self.O0.shape)
 
+    def subset(self, views) -> "Scan":
+        """The same scan restricted to the listed views (in that order); the
+        initial guesses, object size and ground truth are kept."""
+        idx = np.asarray(views, dtype=np.int64)
+        return Scan(np.ascontiguousarray(self.I[idx]), np.ascontiguousarray(self.pos[idx]),
+                    self.P0, self.O0, self.beta, self.P_true, self.O_true,
+                    f"{self.name}[{len(idx)} views]", dict(self.meta))
+
 
 # --------------------------------------------------------------------------
 # random streams

@@ -5,8 +5,16 @@ which the GPU's trajectory is judged).  Cases:
 
   spiral_300     the first 300 views of the 2500-view, 5-mode, 128x128
                  spiral scan (Poisson 1e5 photons per frame)
-  flyscan188_40  the first 40 views of the 10000-view, 4-mode, 188x188 fly
-                 scan (the paper's frame size; Poisson 1e6)
+  flyscan188_40  a block of 5 x 8 views (rows 0-4, columns 0-7) of the
+                 10000-view, 4-mode, 188x188 fly-scan raster (the paper's
+                 frame size; Poisson 1e6)
+
+Beside the error curves and the final probe and object it stores how far
+the perturbed run ends from the base run: in the probe, in the object
+(weighted by the Eq. 5 denominator) and in the modelled intensities
+sum_k |F[P_k O_j]|^2 of every view, which, unlike P and O, are free of the
+ambiguities of the problem (a complex scale c with P -> cP, O -> O/c, and a
+linear phase ramp moved between probe and object).
 
 Calls only the oracle and the seeded input generator.
 
@@ -31,7 +39,8 @@ N_ITER = 100
 PERTURB = 6e-8   # relative size of the complex noise put on the starting probe
 CASES = {
     "spiral_300": lambda: synth.multimode_spiral_128(1, n_frames=300),
-    "flyscan188_40": lambda: synth.flyscan_raster_188(3, n_frames=40),
+    "flyscan188_40": lambda: synth.flyscan_raster_188(3, n_frames=500).subset(
+        [100 * r + c for r in range(5) for c in range(8)]),
 }
 
 
@@ -64,6 +73,11 @@ def trajectory(s, P0):
     return np.array(hist), P, O, den
 
 
+def modelled_intensity(P, O, pos):
+    """sum_k |F[P_k O_window_j]|^2 of every view (the forward model, Eq. 1)."""
+    return np.sum(np.abs(oracle.dft2(oracle.exit_waves(P, O, pos))) ** 2, axis=1)
+
+
 def make(case):
     s = CASES[case]()
     print("oracle run from the cold start", flush=True)
@@ -79,13 +93,16 @@ def make(case):
         return float(np.sqrt(np.sum(wt * np.abs(a - b) ** 2) / np.sum(wt * np.abs(b) ** 2)))
 
     out = out_path(case)
+    model_spread = rel(modelled_intensity(Pp, Op, s.pos), modelled_intensity(P, O, s.pos))
     np.savez_compressed(
         out, eps=h, eps_perturbed=hp, P=P.astype(np.complex64),
         O_box=O[y0:y1, x0:x1].astype(np.complex64), den_box=w.astype(np.float32),
         box=np.array([y0, y1, x0, x1]), perturb=PERTURB,
-        P_spread=rel(Pp, P), O_spread_weighted=rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w))
+        P_spread=rel(Pp, P), O_spread_weighted=rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w),
+        model_spread=model_spread)
     print(f"wrote {out}: eps_P(50) {h[49, 0]:.4e} eps_P(100) {h[99, 0]:.4e}; "
-          f"spread P {rel(Pp, P):.3e} O(weighted) {rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w):.3e}",
+          f"spread P {rel(Pp, P):.3e} O(weighted) {rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w):.3e} "
+          f"modelled intensities {model_spread:.3e}",
           flush=True)
 
 

@@ -1,0 +1,101 @@
+"""The error metric over 100 iterations from the cold start, GPU against the
+FP64 oracle, on strips of two benchmark scans: 300 views of the 5-mode
+128x128 spiral scan (Poisson 1e5) and a 5 x 8 block of the 4-mode 188x188
+fly-scan raster (the paper's frame size, Poisson 1e6).
+
+The oracle's curves and final state come from tests/golden (written by
+tests/golden/make_trajectories.py, which calls only the oracle), together
+with the oracle's own spread: the same 100 iterations from a starting probe
+perturbed by 6e-8 relative (FP32 rounding).  DM is not a contraction, so
+the GPU has to stay about as close to the oracle as the oracle stays to
+itself under that perturbation.  Final probe and object are compared through
+what the problem fixes uniquely -- the modelled intensities
+sum_k |F[P_k O_j]|^2 of every view (Eq. 1) -- since P and O themselves drift
+along the ambiguities of the problem (a complex scale, a phase ramp moved
+between probe and object); P and the weighted O are compared against the
+oracle's spread as well.
+"""
+import importlib.util
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dm_oracle as oracle
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_spec = importlib.util.spec_from_file_location(
+    "make_trajectories", os.path.join(HERE, "golden", "make_trajectories.py"))
+golden = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(golden)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b, w=1.0):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.sqrt(np.sum(w * np.abs(a - b) ** 2) / np.sum(w * np.abs(b) ** 2)))
+
+
+@pytest.mark.parametrize("case", ["spiral_300", "flyscan188_40"])
+def test_trajectory_tracks_the_oracle_over_100_iterations(case):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_10375_amd import dm
+    path = golden.out_path(case)
+    if not os.path.exists(path):
+        pytest.fail(f"{path} missing: run tests/golden/make_trajectories.py {case}")
+    g = np.load(path)
+    s = golden.CASES[case]()
+    n_iter = g["eps"].shape[0]
+    say(f"case trajectory {case}: {s.n_frames} views x {s.n_modes} modes x {s.frame}^2, "
+        f"{n_iter} iterations from the cold start")
+    dev = torch.device("cuda:0")
+    ctx = dm.DMContext(torch.from_numpy(s.I).to(dev), s.pos, torch.from_numpy(s.P0).to(dev),
+                       torch.from_numpy(s.O0).to(dev), beta=s.beta)
+    ctx.iterate(n_iter)
+    eg = np.array([h["eps_probe"] for h in ctx.error_history(1, n_iter)])
+    P_g = ctx.probe().cpu().numpy()
+    O_g = ctx.object().cpu().numpy()
+    ctx.free()
+    eo, ep = g["eps"][:, 0], g["eps_perturbed"][:, 0]
+    dg, dp = np.abs(eg - eo) / eo, np.abs(ep - eo) / eo
+    rg = np.max(np.maximum(eg / eo, eo / eg))
+    rp = np.max(np.maximum(ep / eo, eo / ep))
+    y0, y1, x0, x1 = (int(v) for v in g["box"])
+    P_o, O_box, w = g["P"], g["O_box"], g["den_box"].astype(np.float64)
+    # modelled intensities of every view from each final state
+    O_o = np.array(O_g, dtype=np.complex128)
+    O_o[y0:y1, x0:x1] = O_box
+    model = golden.modelled_intensity
+    m_g = model(P_g.astype(np.complex128), O_g.astype(np.complex128), s.pos)
+    m_o = model(P_o.astype(np.complex128), O_o, s.pos)
+    r_model = rel(m_g, m_o)
+    r_P = rel(P_g, P_o)
+    r_O = rel(O_g[y0:y1, x0:x1], O_box, w)
+    say(f"  err(1) oracle {eo[0]:.5e} gpu {eg[0]:.5e}; err(50) {eo[49]:.4e}/{eg[49]:.4e}; "
+        f"err(100) {eo[-1]:.4e}/{eg[-1]:.4e}")
+    say(f"  deviation gpu: median {np.median(dg):.2e} p90 {np.percentile(dg, 90):.2e} "
+        f"max ratio {rg:.3f}; oracle under 6e-8 noise: median {np.median(dp):.2e} "
+        f"p90 {np.percentile(dp, 90):.2e} max ratio {rp:.3f}")
+    say(f"  final state vs oracle: modelled intensities {r_model:.2e} (oracle spread "
+        f"{float(g['model_spread']):.2e}), P {r_P:.2e} (spread {float(g['P_spread']):.2e}), "
+        f"O weighted {r_O:.2e} (spread {float(g['O_spread_weighted']):.2e})")
+    say(f"  err rises after iteration 50: oracle {eo[-1] > eo[49]}, gpu {eg[-1] > eg[49]}")
+    # the first step starts from identical states
+    assert abs(eg[0] - eo[0]) <= 1e-4 * eo[0]
+    assert np.median(dg) <= max(2 * np.median(dp), 0.01)
+    assert np.percentile(dg, 90) <= max(2 * np.percentile(dp, 90), 0.05)
+    assert rg <= max(1.5 * rp, 1.2)
+    assert abs(eg[-1] - eo[-1]) <= 0.1 * eo[-1]
+    assert r_model <= max(2 * float(g["model_spread"]), 1e-4)
+    assert r_P <= max(2 * float(g["P_spread"]), 1e-3)
+    assert r_O <= max(2 * float(g["O_spread_weighted"]), 1e-3)

@@ -340,3 +340,66 @@ def test_noise_free_reconstruction_converges_small_scan():
     errs = [h["eps_probe"] for h in hist]
     assert all(np.isfinite(errs))
     assert errs[-1] < errs[1]
+
+
+# ---------------------------------------------------------------------------
+# orthogonal probe modes (the mixed-state treatment of the multiple modes)
+# ---------------------------------------------------------------------------
+def test_orthogonal_modes_diagonalise_the_overlap_and_keep_the_mode_power():
+    psi, P, O, pos, I = _random_state(m=4)
+    psi2, Q, lam, V = dm.orthogonalize_modes(psi, P)
+    G = np.einsum("kyx,lyx->kl", np.conj(Q), Q)       # written out, not mode_gram
+    assert np.all(np.diff(lam) <= 0) and lam[-1] >= 0
+    assert np.max(np.abs(G - np.diag(lam))) <= 1e-12 * lam[0]
+    assert np.allclose(V.conj().T @ V, np.eye(4), atol=1e-13)
+    # sum_k |P_k|^2 and the trace of the overlap are unchanged pixel by pixel
+    assert np.max(np.abs(np.sum(np.abs(Q) ** 2, 0) - np.sum(np.abs(P) ** 2, 0))) < 1e-12
+    assert abs(np.sum(lam) - np.sum(np.abs(P) ** 2)) <= 1e-12 * np.sum(lam)
+    # every column's largest entry is real and positive
+    for a in range(4):
+        k = int(np.argmax(np.abs(V[:, a])))
+        assert abs(V[k, a].imag) < 1e-15 and V[k, a].real > 0
+
+
+def test_orthogonal_modes_two_mode_closed_form():
+    """P_0 = a, P_1 = b with |a|^2 = |b|^2 = 2 and <a, b> = 1: the overlap
+    [[2, 1], [1, 2]] has eigenvalues 3 and 1 with eigenvectors (1, 1)/sqrt(2)
+    and (1, -1)/sqrt(2), so the new modes are (a + b)/sqrt(2), (a - b)/sqrt(2)."""
+    a = np.zeros((2, 2), complex)
+    b = np.zeros((2, 2), complex)
+    a[0, 0], a[0, 1] = 1.0, 1.0
+    b[0, 0], b[1, 1] = 1.0, 1.0
+    P = np.stack([a, b])
+    psi = np.stack([P, 2 * P])                         # two views
+    psi2, Q, lam, V = dm.orthogonalize_modes(psi, P)
+    assert np.allclose(lam, [3.0, 1.0], atol=1e-14)
+    assert np.allclose(Q[0], (a + b) / np.sqrt(2), atol=1e-14)
+    assert np.allclose(Q[1], (a - b) / np.sqrt(2), atol=1e-14)
+    assert np.allclose(psi2[1, 0], 2 * (a + b) / np.sqrt(2), atol=1e-14)
+
+
+def test_orthogonal_modes_leave_orthogonal_probes_alone():
+    """Hermite-Gauss modes orthonormal on the grid with distinct weights are
+    already the eigenmodes: V is the identity and nothing moves."""
+    P = synth.hermite_gauss_modes(32, 4.0, synth.HG_ORDERS[:4], [1.0, 0.5, 0.25, 0.12])
+    psi = crand(np.random.default_rng(3), 3, 4, 32, 32)
+    psi2, Q, lam, V = dm.orthogonalize_modes(psi, P)
+    assert np.allclose(V, np.eye(4), atol=1e-6)
+    assert rel(Q, P) < 1e-6 and rel(psi2, psi) < 1e-6
+    assert np.allclose(lam / lam[0], [1.0, 0.5, 0.25, 0.12], rtol=1e-6)
+
+
+def test_iteration_commutes_with_a_unitary_mode_mix():
+    """The DM iteration is equivariant under the unitary mix of the modes
+    that the orthogonalisation applies to probe and views alike: iterating
+    the orthogonalised state gives the mix of the iterated state, and the
+    same object; the modelled intensities sum_k |F[P_k O_j]|^2 do not change."""
+    psi, P, O, pos, I = _random_state(m=3)
+    psi2, Q, lam, V = dm.orthogonalize_modes(psi, P)
+    a = dm.iterate(psi, P, O, pos, I, 0.8)
+    b = dm.iterate(psi2, Q, O, pos, I, 0.8)
+    assert rel(b[2], a[2]) < 1e-12
+    assert rel(b[1], np.einsum("ka,kyx->ayx", V, a[1])) < 1e-12
+    assert rel(b[0], np.einsum("ka,jkyx->jayx", V, a[0])) < 1e-12
+    model = lambda PP: np.sum(np.abs(dm.dft2(dm.exit_waves(PP, O, pos))) ** 2, axis=1)  # noqa: E731
+    assert rel(model(Q), model(P)) < 1e-13

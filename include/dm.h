@@ -6,8 +6,11 @@
  *
  * Problem (Section II, Eqs. 1-2): N views j with integer top-left corners
  * (y_j, x_j), measured intensities I_j, probe modes P_k (k < M) and one object
- * O (a single object mode).  The exit wave of view j, mode k is
- * psi_{j,k} = P_k * O[window_j].  One iteration (dm_iterate) computes:
+ * O (by default a single object mode).  The exit wave of view j, mode k is
+ * psi_{j,k} = P_k * O[window_j].  With L object modes O_l (dm_desc.n_obj_modes)
+ * the views hold the pairs psi_{j,(k,l)} = P_k * O_l[window_j] at mode index
+ * l M + k, F_c sums over all pairs, Eq. 5 updates each O_l from its pairs and
+ * Eq. 4 sums over l as well.  One iteration (dm_iterate) computes:
  *   1. views   psi <- psi + beta (F^-1 F_c[2 P O - psi] - P O)       (Eq. 3)
  *              F_c rescales every mode of a view by
  *              sqrt(I_j / sum_k |F[.]_k|^2) and keeps the phase  (F_c, Eq. 3)
@@ -23,8 +26,8 @@
  *   I      float32   [N][F][F]
  *   pos    int32     [N][2]      (y, x) top-left of each F x F window
  *   probe  complex64 [M][F][F]
- *   object complex64 [H][W]
- *   psi    complex64 [N][M][F][F]
+ *   object complex64 [H][W], or [L][H][W] with L object modes
+ *   psi    complex64 [N][M][F][F], or [N][L M][F][F] with L object modes
  *
  * Memory ownership: every device buffer is the caller's.  I is read in place
  * and must stay alive and unchanged until dm_free.  probe0/object0 are
@@ -112,16 +115,26 @@ typedef enum {
                                     not formed there and eps_psi is reported
                                     as NaN.                                 */
 
-#define DM_FLAG_PROBE_FIRST 16u  /* overlap projection in the swapped order
-                                    the paper describes (Section III, the
-                                    remark on the object embedding): the
+#define DM_FLAG_PROBE_FIRST 16u  /* overlap projection probe first: the
                                     probe (Eq. 4) from the new views and the
                                     current object, then the object (Eq. 5)
-                                    from the new views and the new probe.
-                                    Default: object first, then probe from
-                                    the new object.  Costs one more read of
-                                    psi' (the object numerators are formed
-                                    again with the new probe).              */
+                                    from the new views and the new probe,
+                                    the order Eqs. 4-5 are written in, i.e.
+                                    the order before the swap Section III
+                                    describes.  The default, object first
+                                    and then the probe from the new object,
+                                    is the swapped order: the object update
+                                    of a view then needs only that view's
+                                    new exit waves and the current probe, so
+                                    every view's contribution is formed in
+                                    the view kernel right after its update
+                                    (the paper's overlap of one batch's
+                                    object embedding with the next batch's
+                                    view update, at the grain of single
+                                    views) and only the gather over views is
+                                    left.  Probe first costs one more read
+                                    of psi' (the object numerators are
+                                    formed again with the new probe).       */
 
 /* Phases of one iteration, in launch order (indices of dm_phase_times;
  * with DM_FLAG_PROBE_FIRST the two probe phases run before the object
@@ -148,9 +161,18 @@ typedef struct {
   float beta;         /* relaxation, 0 <= beta <= 1 (Eq. 3; usually 0.8) */
   int32_t precision;  /* dm_precision                                    */
   uint32_t flags;     /* DM_FLAG_* bits, others must be 0                */
+  int32_t n_obj_modes; /* L: object modes of Eqs. 1-5; 0 or 1 = one.  L > 1
+                         (at most DM_MAX_OBJ_MODES, and L M at most
+                         DM_MAX_PAIRS) runs the FP32 three-kernel path
+                         with power-of-two F (the spectrum buffer then
+                         holds N L M F^2 complex values); other precisions
+                         and frame sizes give DM_E_UNSUPPORTED, and so
+                         does the warm start                             */
 } dm_desc;
 
 #define DM_MAX_MODES 16
+#define DM_MAX_OBJ_MODES 4
+#define DM_MAX_PAIRS 32
 #define DM_MAX_PROBE_CHUNKS 64
 
 /* dm_tuning.view_path values */
@@ -229,7 +251,8 @@ dm_status dm_init(dm_ctx** out, const dm_desc* desc, const float* I_dev,
  * ring of the last 4096 iterations. */
 dm_status dm_iterate(dm_ctx* ctx, int32_t n_iter);
 
-/* Enqueue a device-to-device copy of the current object, complex64 [H][W]. */
+/* Enqueue a device-to-device copy of the current object, complex64 [H][W]
+ * ([L][H][W] with L object modes). */
 dm_status dm_get_object(dm_ctx* ctx, void* dst_dev);
 
 /* Enqueue a device-to-device copy of the current probe, complex64 [M][F][F]. */
@@ -256,14 +279,15 @@ dm_status dm_error_history(dm_ctx* ctx, int32_t first, int32_t count,
 int32_t dm_iterations(const dm_ctx* ctx);
 
 /* Copy the full state out (device destinations; any may be NULL to skip):
- * psi [N][M][F][F], probe [M][F][F], object [H][W]; *iter_host gets the
- * iteration count.  Synchronises. */
+ * psi [N][M][F][F], probe [M][F][F], object [H][W] (with L object modes psi
+ * [N][L M][F][F] and object [L][H][W]); *iter_host gets the iteration count.
+ * Synchronises. */
 dm_status dm_get_state(dm_ctx* ctx, void* psi_dst_dev, void* probe_dst_dev,
                        void* object_dst_dev, int32_t* iter_host);
 
-/* Replace the state (device sources; all three required) and set the
- * iteration count: exact resume, or a one-step comparison from a given
- * state.  Asynchronous. */
+/* Replace the state (device sources in the layouts of dm_get_state; all
+ * three required) and set the iteration count: exact resume, or a one-step
+ * comparison from a given state.  Asynchronous. */
 dm_status dm_set_state(dm_ctx* ctx, const void* psi_dev, const void* probe_dev,
                        const void* object_dev, int32_t iter);
 
@@ -274,7 +298,7 @@ dm_status dm_set_state(dm_ctx* ctx, const void* psi_dev, const void* probe_dev,
 dm_status dm_phase_times(dm_ctx* ctx, double* ms_host, int32_t* n_iter_host);
 
 /* ---- batches: many scans, one launch chain per iteration ------------------
- * All scans of a batch share F, M, precision and flags; each has its own
+ * All scans of a batch share F, M, L, precision and flags; each has its own
  * views, positions, intensities, probe, object, beta and error ring.  One
  * dm_iterate advances every scan by one DM iteration with one launch per
  * phase for the whole batch (one graph launch with DM_FLAG_GRAPH).  The
@@ -297,6 +321,28 @@ dm_status dm_scan_error_history(dm_ctx* ctx, int32_t scan, int32_t first,
                                 int32_t count, dm_errors* out_host);
 dm_status dm_scan_mode_power(dm_ctx* ctx, int32_t scan, double* power_host);
 
+/* ---- orthogonal probe modes ----------------------------------------------- */
+/* Replace the probe modes by the eigenmodes of their overlap matrix
+ * G[k][l] = sum_r conj(P_k(r)) P_l(r).  With G = V diag(lam) V^H, lam
+ * descending, mode a becomes sum_k V[k][a] P_k and every view is mixed the
+ * same way, psi_{j,a} <- sum_k V[k][a] psi_{j,k}.  The intensity model of
+ * Eq. 1 is a sum over modes, so the modulus projection F_c and the updates
+ * of Eqs. 4-5 do not change under such a unitary mix: the iteration goes on
+ * from an equivalent state whose modes are orthogonal and ordered by power
+ * (Section II treats the modes as mutually incoherent and cites the
+ * mixed-state method, which works with these eigenmodes).  Each column of V
+ * gets a fixed phase: its entry of largest modulus (the first such) is made
+ * real and positive.  Overlaps, eigen-decomposition (cyclic Jacobi) and mix
+ * run in FP64 on the device; the results are rounded to FP32 once.
+ *   power_host  NULL, or host array of M doubles: the eigenvalues, i.e. the
+ *               new modes' powers sum_r |P_a(r)|^2, descending (the call then
+ *               synchronises with the context's stream).
+ * Enqueued on the context's stream.  The iteration counter and the error
+ * ring are kept.  DM_E_ARG: scan index out of range. */
+dm_status dm_orthogonalize_modes(dm_ctx* ctx, double* power_host);
+dm_status dm_scan_orthogonalize_modes(dm_ctx* ctx, int32_t scan, double* power_host);
+
+
 /* ---- warm start ------------------------------------------------------------ */
 /* Replace the object with patches stitched by the object update (Section II,
  * Eq. 5) applied to the exit waves psi_{j,k} = P_k * patch_j with the current
@@ -306,7 +352,8 @@ dm_status dm_scan_mode_power(dm_ctx* ctx, int32_t scan, double* power_host);
  *   patches_dev  complex64 [N][F][F], device, caller-owned; patch j is the
  *                object guess under view j's window, indexed like the frame.
  * Enqueued on the context's stream; the iteration counter is kept.
- * DM_E_ARG: NULL or misaligned patches, or a scan index out of range. */
+ * DM_E_ARG: NULL or misaligned patches, or a scan index out of range;
+ * DM_E_UNSUPPORTED: more than one object mode. */
 dm_status dm_warm_start(dm_ctx* ctx, const void* patches_dev);
 dm_status dm_scan_warm_start(dm_ctx* ctx, int32_t scan, const void* patches_dev);
 

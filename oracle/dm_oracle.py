@@ -6,8 +6,11 @@ calls it, and it shares no code, tables or constants with the GPU path.
 
 It follows Section II of Dong, Fang et al., "High-Performance Multi-Mode
 Ptychography Reconstruction on Distributed GPUs" (arXiv:1808.10375), step by
-step, in complex128, with a single object mode (M_O = 1; the paper knows no
-case where more help) so the mode index k runs over probe modes only:
+step, in complex128.  The formulas below are written for one object mode
+(M_O = 1, the paper knows no case where more help), so the mode index k runs
+over probe modes; an object of shape [L][H][W] gives L object modes, the
+views then carry the pairs (k, l) of Eqs. 1-5 at index l*M + k, F_c sums over
+all pairs, Eq. 5 updates every O_l with its own views and Eq. 4 sums over l:
 
   exit wave       phi_{j,k} = P_k * O[window_j]                       (Eq. 2)
   view update     psi <- psi + beta * (F^-1 F_c[2 phi - psi] - phi)   (Eq. 3)
@@ -24,9 +27,12 @@ case where more help) so the mode index k runs over probe modes only:
 
 Readings where the paper is silent (each also listed in the design notes):
   * order: views first, then the object from (psi', P_old), then the probe
-    from (psi', O_new); one object/probe pass per iteration.  The paper's
-    Section III describes swapping the P and O order as an optimisation, so
-    this order is the default one.
+    from (psi', O_new); one object/probe pass per iteration.  Section III
+    describes swapping the P and O updates as an optimisation: from the
+    order the equations are written in (probe first) to object first, which
+    lets the object embedding of one batch of views overlap the view update
+    of the next.  The swapped order is the default here; probe first is the
+    option probe_first.
   * F is the unnormalised forward DFT with exp(-2 pi i k n / F); F^-1 carries
     1/F^2; DC sits at index [0, 0] (no fftshift).
   * where sum_k |F[.]_k|^2 == 0 every mode's spectrum is 0 there, and the
@@ -74,10 +80,14 @@ def windows(O: np.ndarray, pos: np.ndarray, f: int) -> np.ndarray:
 
 
 def exit_waves(P: np.ndarray, O: np.ndarray, pos: np.ndarray) -> np.ndarray:
-    """phi_{j,k} = P_k * O[window_j] (Eq. 2) -> [N][M][F][F]."""
+    """phi_{j,k} = P_k * O[window_j] (Eq. 2) -> [N][M][F][F]; with object
+    modes O [L][H][W], phi_{j,(k,l)} = P_k * O_l[window_j] at index l*M + k
+    -> [N][L*M][F][F]."""
     P = np.asarray(P, dtype=np.complex128)
     O = np.asarray(O, dtype=np.complex128)
-    return P[None, :, :, :] * windows(O, pos, P.shape[-1])[:, None, :, :]
+    if O.ndim == 2:
+        return P[None, :, :, :] * windows(O, pos, P.shape[-1])[:, None, :, :]
+    return np.concatenate([exit_waves(P, O[l], pos) for l in range(O.shape[0])], axis=1)
 
 
 # ---------------------------------------------------------------------------
@@ -87,7 +97,8 @@ def constrained_ft(spectra: np.ndarray, I: np.ndarray) -> np.ndarray:
     """Replace the computed amplitude by the measured one, keeping the phase:
     every mode k of view j is multiplied by sqrt(I_j / sum_k |spectra_k|^2).
 
-    spectra [N][M][F][F] (already transformed), I [N][F][F] -> same shape.
+    spectra [N][M][F][F] (already transformed; with object modes the second
+    axis runs over all L*M pairs (k, l)), I [N][F][F] -> same shape.
     Where the mode sum is zero all modes are zero and the result is zero."""
     spectra = np.asarray(spectra, dtype=np.complex128)
     I = np.maximum(np.asarray(I, dtype=np.float64), 0.0)
@@ -125,9 +136,16 @@ def object_update(psi, P, O_old, pos):
 
     Numerator and denominator are accumulated by embedding each view's
     F x F window into the object, in ascending j.  Pixels with a zero
-    denominator keep O_old.  Returns (O_new, denominator)."""
+    denominator keep O_old.  Returns (O_new, denominator).  With object
+    modes (O_old [L][H][W]) object mode l takes the views of the pairs
+    (k, l), psi[:, l*M:(l+1)*M]; the denominator is the same for every l."""
     psi = np.asarray(psi, dtype=np.complex128)
     P = np.asarray(P, dtype=np.complex128)
+    if np.ndim(O_old) == 3:
+        m = P.shape[0]
+        parts = [object_update(psi[:, l * m:(l + 1) * m], P, O_old[l], pos)
+                 for l in range(O_old.shape[0])]
+        return np.stack([o for o, _ in parts]), parts[0][1]
     f = P.shape[-1]
     num = np.zeros(O_old.shape, dtype=np.complex128)
     den = np.zeros(O_old.shape, dtype=np.float64)
@@ -148,16 +166,22 @@ def object_update(psi, P, O_old, pos):
 def probe_update(psi, O, P_old, pos):
     """P_k = sum_j conj(O[window_j]) psi_{j,k} / sum_j |O[window_j]|^2 (Eq. 4).
 
-    Pixels with a zero denominator keep P_old.  Returns (P_new, denominator)."""
+    Pixels with a zero denominator keep P_old.  Returns (P_new, denominator).
+    With object modes (O [L][H][W]) both sums also run over l:
+    P_k = sum_l sum_j conj(O_l[window_j]) psi_{j,(k,l)}
+          / sum_l sum_j |O_l[window_j]|^2."""
     psi = np.asarray(psi, dtype=np.complex128)
     O = np.asarray(O, dtype=np.complex128)
+    objs = O[None] if O.ndim == 2 else O
+    m = P_old.shape[0]
     f = P_old.shape[-1]
     num = np.zeros(P_old.shape, dtype=np.complex128)
     den = np.zeros(P_old.shape[-2:], dtype=np.float64)
-    for j, (y, x) in enumerate(np.asarray(pos)):
-        w = O[y:y + f, x:x + f]
-        num += np.conj(w)[None] * psi[j]
-        den += np.abs(w) ** 2
+    for l, Ol in enumerate(objs):
+        for j, (y, x) in enumerate(np.asarray(pos)):
+            w = Ol[y:y + f, x:x + f]
+            num += np.conj(w)[None] * psi[j, l * m:(l + 1) * m]
+            den += np.abs(w) ** 2
     P_new = np.array(P_old, dtype=np.complex128)
     ok = den > 0
     P_new[:, ok] = num[:, ok] / den[ok]
@@ -187,9 +211,9 @@ def rel_change(new, old, mask=None) -> float:
 def iterate(psi, P, O, pos, I, beta, probe_first: bool = False):
     """One DM iteration: views (Eq. 3), then object (Eq. 5) from the new
     views and the old probe, then probe (Eq. 4) from the new views and the
-    new object.  With probe_first, the order Section III describes as an
-    optimisation: probe (Eq. 4) from the new views and the old object, then
-    object (Eq. 5) from the new views and the new probe.
+    new object (Section III's swapped order).  With probe_first, the order
+    before that swap: probe (Eq. 4) from the new views and the old object,
+    then object (Eq. 5) from the new views and the new probe.
     Returns (psi', P', O', errors)."""
     pos = np.asarray(pos)
     P = np.asarray(P, dtype=np.complex128)
@@ -244,7 +268,11 @@ def orthogonalize_modes(psi, P):
         k = int(np.argmax(np.abs(V[:, a])))
         V[:, a] *= np.conj(V[k, a]) / abs(V[k, a])
     Q = np.einsum("ka,kyx->ayx", V, P)
-    psi_new = np.einsum("ka,jkyx->jayx", V, psi)
+    # views [N][L*M][F][F]: the probe modes are mixed within each object mode
+    n, c = psi.shape[:2]
+    m = P.shape[0]
+    psi_new = np.einsum("ka,jlkyx->jlayx", V,
+                        psi.reshape(n, c // m, m, *psi.shape[2:])).reshape(psi.shape)
     return psi_new, Q, lam, V
 
 

@@ -19,6 +19,7 @@
 #include "dm_mixed.hpp"
 #include "dm_order.hpp"
 #include "dm_modes.hpp"
+#include "dm_ortho.hpp"
 
 using dmk::DevErrors;
 using dmk::ScanDev;
@@ -48,8 +49,17 @@ int default_chunks(int F) {
 
 bool is_bf16x3(const dm_desc& d) { return d.precision == DM_BF16X3_DFT; }
 
+// object modes L (n_obj_modes 0 means 1)
+int obj_modes(const dm_desc& d) { return d.n_obj_modes > 1 ? d.n_obj_modes : 1; }
+
+// frames per view: the L M pairs (probe mode k, object mode l) of Eqs. 1-5
+int frames_per_view(const dm_desc& d) { return d.n_modes * obj_modes(d); }
+
+// Object modes run on the three-kernel path only (its kernels index the
+// (k, l) pairs); so do F = 256 and the mixed-radix sizes.
 bool has_spectrum_buffer(const dm_desc& d) {
-  return d.frame == 256 || is_mixed(d.frame) || (d.flags & DM_FLAG_MULTIPASS) || is_bf16x3(d);
+  return d.frame == 256 || is_mixed(d.frame) || (d.flags & DM_FLAG_MULTIPASS) || is_bf16x3(d) ||
+         obj_modes(d) > 1;
 }
 
 dm_tuning default_tuning(const dm_desc& d) {
@@ -127,7 +137,7 @@ size_t mix_cols_lds_bytes(int F, int M, int cb) {
 // ---------------------------------------------------------------------------
 struct ScanLayout {
   size_t psi, opart, gscr, tspec, P, O, D, num_part, den_part, err_psi, err_obj, err_probe,
-      ring, counter, mode_pow, pos, order, tile_ptr, tile_views, bytes;
+      ring, counter, mode_pow, ortho, pos, order, tile_ptr, tile_views, bytes;
   int ntiles16, nnz16, n_psi_parts_fused, n_psi_parts_multi;
 };
 
@@ -140,7 +150,8 @@ int nnz_bound(const dm_desc& d, int T) {
 
 ScanLayout scan_layout(const dm_desc& d) {
   ScanLayout L{};
-  const size_t N = d.n_frames, M = d.n_modes, F = d.frame, FF = F * F;
+  const size_t N = d.n_frames, M = frames_per_view(d), F = d.frame, FF = F * F;
+  const size_t NL = obj_modes(d);
   const size_t c8 = 8;
   // eps_psi partial sums per view: 1 (fused), F / row block (three-kernel
   // FFT path), 2 (BF16x3 path, two row halves)
@@ -155,21 +166,22 @@ ScanLayout scan_layout(const dm_desc& d) {
     return o;
   };
   L.psi = take(N * M * FF * c8);
-  L.opart = take(N * FF * c8);
+  L.opart = take(N * NL * FF * c8);
   L.gscr = d.frame <= 128 ? take(N * FF * 4) : 0;
   L.tspec = has_spectrum_buffer(d) ? take(N * M * FF * c8) : 0;
   L.P = take(M * FF * c8);
-  L.O = take((size_t)d.obj_h * d.obj_w * c8);
+  L.O = take(NL * d.obj_h * d.obj_w * c8);
   L.D = take(FF * 4);
-  L.num_part = take((size_t)DM_MAX_PROBE_CHUNKS * M * FF * c8);
+  L.num_part = take((size_t)DM_MAX_PROBE_CHUNKS * d.n_modes * FF * c8);
   L.den_part = take((size_t)DM_MAX_PROBE_CHUNKS * FF * 4);
   L.err_psi = take((size_t)std::max({L.n_psi_parts_fused, L.n_psi_parts_multi, 2 * (int)N}) *
                    2 * 4);
-  L.err_obj = take((size_t)L.ntiles16 * 2 * 4);
-  L.err_probe = take((size_t)n_pblk((int)F) * M * 2 * 4);
+  L.err_obj = take((size_t)L.ntiles16 * NL * 2 * 4);
+  L.err_probe = take((size_t)n_pblk((int)F) * d.n_modes * 2 * 4);
   L.ring = take(sizeof(DevErrors) * dmk::kRing);
   L.counter = take(sizeof(int));
   L.mode_pow = take(DM_MAX_MODES * sizeof(double));
+  L.ortho = take(dmk::kOrthoScratchBytes);
   L.pos = take(N * 2 * 4);
   L.order = take(N * 4);
   L.tile_ptr = take(((size_t)L.ntiles16 + 1) * 4);
@@ -270,6 +282,22 @@ dm_status validate_desc(const dm_desc* d, std::string& why) {
     why = "object larger than 2^28 pixels";
     return DM_E_UNSUPPORTED;
   }
+  if (d->n_obj_modes < 0) { why = "n_obj_modes must be >= 0"; return DM_E_ARG; }
+  if (obj_modes(*d) > 1) {
+    const int L = obj_modes(*d);
+    if (L > DM_MAX_OBJ_MODES || L * d->n_modes > DM_MAX_PAIRS) {
+      why = "object modes: at most 4, and at most 32 (probe mode, object mode) pairs";
+      return DM_E_UNSUPPORTED;
+    }
+    if (d->precision != DM_FP32_FFT || is_mixed(d->frame)) {
+      why = "object modes run on the FP32 three-kernel path with power-of-two frames";
+      return DM_E_UNSUPPORTED;
+    }
+    if ((double)L * d->obj_h * d->obj_w * 8.0 >= 2147483648.0) {
+      why = "object modes larger than 2^28 pixels together";
+      return DM_E_UNSUPPORTED;
+    }
+  }
   if ((double)d->n_frames * d->frame * d->frame >= 2147483648.0) {
     why = "more than 2^31 detector pixels in one scan";
     return DM_E_UNSUPPORTED;
@@ -286,8 +314,10 @@ dm_status validate_batch(int n_scans, const dm_desc* d, std::string& why) {
       return st;
     }
     if (d[s].frame != d[0].frame || d[s].n_modes != d[0].n_modes ||
-        d[s].precision != d[0].precision || d[s].flags != d[0].flags) {
-      why = "all scans of a batch need the same frame, n_modes, precision and flags";
+        d[s].precision != d[0].precision || d[s].flags != d[0].flags ||
+        obj_modes(d[s]) != obj_modes(d[0])) {
+      why = "all scans of a batch need the same frame, n_modes, n_obj_modes, precision and "
+            "flags";
       return DM_E_ARG;
     }
   }
@@ -313,6 +343,7 @@ struct dm_ctx {
   std::vector<Scan> scans;
   CtxLayout CL;
   int F = 0, M = 0;
+  int L = 1;  // object modes (the views hold L M frames)
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -522,7 +553,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
                     : t.view_path == DM_VIEWS_THREE_KERNEL ? L.n_psi_parts_multi
                                     : L.n_psi_parts_fused;
     v.beta = S.d.beta;
-    v.pad = 0;
+    v.L = obj_modes(S.d);
     for (int i = 0; i < S.ntiles; ++i) tmap.push_back(make_int2(s, i));
     for (int i = 0; i < S.C; ++i) cmap.push_back(make_int2(s, i));
   }
@@ -540,8 +571,8 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
                                 : reinterpret_cast<const void*>(dmk::k_mix_cols<200>);
     DM_HIP(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   } else if (t.view_path == DM_VIEWS_THREE_KERNEL) {
-    const int lds =
-        (int)cols_lds_bytes(c->F, c->M, cols_per_block(c->F, c->M));
+    const int MT = c->M * c->L;
+    const int lds = (int)cols_lds_bytes(c->F, MT, cols_per_block(c->F, MT));
     DM_HIP(c, set_cols_lds(c->F, lds));
   }
   DM_HIP(c, hipStreamSynchronize(c->stream));
@@ -596,14 +627,15 @@ dm_status launch_views_fused(dm_ctx* c) {
 template <int F>
 dm_status launch_views_multipass(dm_ctx* c) {
   constexpr int B = F / 16, RB = dmk::RowCfg<F>::RB, NT = dmk::RowCfg<F>::NT;
-  const int M = c->M;
-  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views * M, F / RB), dim3(NT), 0,
+  const int M = c->M, MT = c->M * c->L;  // probe modes, frames per view
+  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views * MT, F / RB), dim3(NT), 0,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_rows_fwd");
-  const int cb = cols_per_block(F, M);
-  const size_t lds = cols_lds_bytes(F, M, cb);
-  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views * (F / cb)), dim3(cb * B * M), lds,
-                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M, cb);
+  // the column kernel sums the modulus over all MT frames of a view
+  const int cb = cols_per_block(F, MT);
+  const size_t lds = cols_lds_bytes(F, MT, cb);
+  hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views * (F / cb)), dim3(cb * B * MT), lds,
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), MT, cb);
   DM_LAUNCHED(c, "k_cols");
   hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,
                      c->scan_dev(), c->vmap(), c->tw(), M);
@@ -799,16 +831,16 @@ dm_status launch_iteration(dm_ctx* c, bool psi_err) {
   auto object = [&]() -> dm_status {
     DM_TRY(phase_begin(c, DM_PHASE_OBJECT, &mk));
     if (c->flags & DM_FLAG_PROBE_FIRST) {
-      hipLaunchKernelGGL(dmk::k_view_numerators, dim3(c->total_views, nb), dim3(256), 0,
+      hipLaunchKernelGGL(dmk::k_view_numerators, dim3(c->total_views, nb, c->L), dim3(256), 0,
                          c->stream, c->scan_dev(), c->vmap(), M, FF);
       DM_LAUNCHED(c, "k_view_numerators");
     }
     if (c->tune.obj_tile == 16)
-      hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
-                         c->scan_dev(), c->tmap(), F);
+      hipLaunchKernelGGL((dmk::k_object<16, kObjGroups>), dim3(c->total_tiles, c->L),
+                         dim3(256 * kObjGroups), 0, c->stream, c->scan_dev(), c->tmap(), F);
     else
-      hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(c->total_tiles), dim3(256 * kObjGroups), 0, c->stream,
-                         c->scan_dev(), c->tmap(), F);
+      hipLaunchKernelGGL((dmk::k_object<32, kObjGroups>), dim3(c->total_tiles, c->L),
+                         dim3(256 * kObjGroups), 0, c->stream, c->scan_dev(), c->tmap(), F);
     DM_LAUNCHED(c, "k_object");
     return phase_end(c, mk);
   };
@@ -867,16 +899,19 @@ dm_status init_scan_state(dm_ctx* c, int s) {
   auto& S = c->scans[s];
   const ScanLayout& L = S.L;
   const size_t M = S.d.n_modes, FF = (size_t)S.d.frame * S.d.frame;
+  const int NL = obj_modes(S.d);
   DM_HIP(c, hipMemcpyAsync(c->sat<float2>(s, L.P), S.P0, M * FF * 8, hipMemcpyDeviceToDevice,
                            c->stream));
-  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(s, L.O), S.O0, (size_t)S.d.obj_h * S.d.obj_w * 8,
-                           hipMemcpyDeviceToDevice, c->stream));
+  DM_HIP(c, hipMemcpyAsync(c->sat<float2>(s, L.O), S.O0,
+                           (size_t)NL * S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
   hipLaunchKernelGGL(dmk::k_fill_int, dim3(1), dim3(64), 0, c->stream, c->sat<int>(s, L.counter),
                      1, 0);
   DM_LAUNCHED(c, "k_fill_int");
-  hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes), dim3(256), 0, c->stream,
-                     c->sat<float2>(s, L.psi), c->sat<float2>(s, L.P), c->sat<float2>(s, L.O),
-                     c->sat<int>(s, L.pos), S.d.n_modes, S.d.frame, S.d.obj_w);
+  hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes * NL), dim3(256), 0,
+                     c->stream, c->sat<float2>(s, L.psi), c->sat<float2>(s, L.P),
+                     c->sat<float2>(s, L.O), c->sat<int>(s, L.pos), S.d.n_modes, S.d.frame,
+                     S.d.obj_w, NL, S.d.obj_h);
   DM_LAUNCHED(c, "k_init_psi");
   hipLaunchKernelGGL(dmk::k_mode_power, dim3((FF + 255) / 256), dim3(256), 0, c->stream,
                      c->sat<float2>(s, L.P), c->sat<float>(s, L.D), S.d.n_modes, (int)FF);
@@ -885,6 +920,27 @@ dm_status init_scan_state(dm_ctx* c, int s) {
 }
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Orthogonal probe modes (dm_ortho.hpp): the modes' Gram matrix, its
+// eigen-decomposition and the mix of the probe and of every view, enqueued
+// on `st`; `scr` holds dmk::kOrthoScratchBytes; the eigenvalues (the new
+// modes' powers, descending) go to lam_dev if it is not NULL.
+hipError_t launch_ortho(float2* P, float2* psi, int n_views, int M, int F, void* scr,
+                        double* lam_dev, hipStream_t st) {
+  const int FF = F * F, npairs = M * (M + 1) / 2;
+  double2* w = reinterpret_cast<double2*>(scr);
+  hipLaunchKernelGGL(dmk::k_gram_partial, dim3(npairs, dmk::kOrthoChunks), dim3(256), 0, st, P,
+                     M, FF, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dmk::k_ortho_eig, dim3(1), dim3(64), 0, st, M, w, lam_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int sets = n_views + 1;
+  hipLaunchKernelGGL(dmk::k_mix_modes, dim3((FF + 255) / 256, std::min(sets, 65535)), dim3(256), 0,
+                     st, psi, P, n_views, M, FF, w);
+  return hipGetLastError();
+}
 
 dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const float* const* Is,
                      const int32_t* const* poss, const void* const* P0s, const void* const* O0s,
@@ -940,6 +996,7 @@ dm_status batch_init(dm_ctx** out, int n_scans, const dm_desc* descs, const floa
   c->CL = CL;
   c->F = descs[0].frame;
   c->M = descs[0].n_modes;
+  c->L = obj_modes(descs[0]);
   c->flags = descs[0].flags;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->ws = reinterpret_cast<char*>(ws);
@@ -1118,6 +1175,10 @@ dm_status valid_tuning(dm_ctx* c, const dm_tuning& t) {
     c->err = "frames above 128 only have the three-kernel path";
     return DM_E_ARG;
   }
+  if (t.view_path != DM_VIEWS_THREE_KERNEL && c->L > 1) {
+    c->err = "object modes only have the three-kernel path";
+    return DM_E_ARG;
+  }
   return DM_OK;
 }
 
@@ -1206,7 +1267,8 @@ dm_status dm_scan_get_object(dm_ctx* c, int32_t scan, void* dst) {
   if (s != DM_OK) return s;
   if (!dst) { c->err = "dst is NULL"; return DM_E_ARG; }
   const auto& S = c->scans[scan];
-  DM_HIP(c, hipMemcpyAsync(dst, c->sat<float2>(scan, S.L.O), (size_t)S.d.obj_h * S.d.obj_w * 8,
+  DM_HIP(c, hipMemcpyAsync(dst, c->sat<float2>(scan, S.L.O),
+                           (size_t)obj_modes(S.d) * S.d.obj_h * S.d.obj_w * 8,
                            hipMemcpyDeviceToDevice, c->stream));
   return DM_OK;
 }
@@ -1241,6 +1303,34 @@ dm_status dm_mode_power(dm_ctx* c, double* power_host) {
   return dm_scan_mode_power(c, 0, power_host);
 }
 
+dm_status dm_scan_orthogonalize_modes(dm_ctx* c, int32_t scan, double* power_host) {
+  dm_status s = check_scan(c, scan);
+  if (s != DM_OK) return s;
+  const auto& S = c->scans[scan];
+  const ScanLayout& L = S.L;
+  const int M = S.d.n_modes, F = S.d.frame;
+  double* lam = c->sat<double>(scan, L.mode_pow);
+  // the views' frames come in runs of M probe modes, one run per object mode
+  DM_HIP(c, launch_ortho(c->sat<float2>(scan, L.P), c->sat<float2>(scan, L.psi),
+                         S.d.n_frames * obj_modes(S.d), M, F, c->sat<void>(scan, L.ortho), lam,
+                         c->stream));
+  // the mode power D = sum_k |P_k|^2 of the Eq. 5 normaliser, formed again
+  // from the mixed modes
+  hipLaunchKernelGGL(dmk::k_mode_power, dim3((F * F + 255) / 256), dim3(256), 0, c->stream,
+                     c->sat<float2>(scan, L.P), c->sat<float>(scan, L.D), M, F * F);
+  DM_LAUNCHED(c, "k_mode_power");
+  if (power_host) {
+    DM_HIP(c, hipMemcpyAsync(power_host, lam, (size_t)M * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    DM_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return DM_OK;
+}
+
+dm_status dm_orthogonalize_modes(dm_ctx* c, double* power_host) {
+  return dm_scan_orthogonalize_modes(c, 0, power_host);
+}
+
 dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
   dm_status s = check_scan(c, scan);
   if (s != DM_OK) return s;
@@ -1249,6 +1339,10 @@ dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
     return DM_E_ARG;
   }
   auto& S = c->scans[scan];
+  if (obj_modes(S.d) > 1) {
+    c->err = "the warm start replaces a single object mode";
+    return DM_E_UNSUPPORTED;
+  }
   const ScanLayout& L = S.L;
   const int FF = S.d.frame * S.d.frame;
   const size_t total = (size_t)S.d.n_frames * FF;
@@ -1271,7 +1365,7 @@ dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
   hipLaunchKernelGGL(dmk::k_init_psi, dim3(S.d.n_frames * S.d.n_modes), dim3(256), 0, c->stream,
                      c->sat<float2>(scan, L.psi), c->sat<float2>(scan, L.P),
                      c->sat<float2>(scan, L.O), c->sat<int>(scan, L.pos), S.d.n_modes,
-                     S.d.frame, S.d.obj_w);
+                     S.d.frame, S.d.obj_w, 1, S.d.obj_h);
   DM_LAUNCHED(c, "k_init_psi");
   return DM_OK;
 }
@@ -1327,16 +1421,17 @@ dm_status dm_get_state(dm_ctx* c, void* psi_dst, void* probe_dst, void* object_d
   }
   const auto& S = c->scans[0];
   const size_t FF = (size_t)S.d.frame * S.d.frame;
+  const size_t NL = obj_modes(S.d);
   if (psi_dst)
     DM_HIP(c, hipMemcpyAsync(psi_dst, c->sat<float2>(0, S.L.psi),
-                             (size_t)S.d.n_frames * S.d.n_modes * FF * 8,
+                             (size_t)S.d.n_frames * S.d.n_modes * NL * FF * 8,
                              hipMemcpyDeviceToDevice, c->stream));
   if (probe_dst)
     DM_HIP(c, hipMemcpyAsync(probe_dst, c->sat<float2>(0, S.L.P), (size_t)S.d.n_modes * FF * 8,
                              hipMemcpyDeviceToDevice, c->stream));
   if (object_dst)
     DM_HIP(c, hipMemcpyAsync(object_dst, c->sat<float2>(0, S.L.O),
-                             (size_t)S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
+                             NL * S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
                              c->stream));
   DM_HIP(c, hipStreamSynchronize(c->stream));
   if (iter_host) *iter_host = c->iters;
@@ -1357,13 +1452,14 @@ dm_status dm_set_state(dm_ctx* c, const void* psi_src, const void* probe_src,
   }
   const auto& S = c->scans[0];
   const size_t FF = (size_t)S.d.frame * S.d.frame;
+  const size_t NL = obj_modes(S.d);
   DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.psi), psi_src,
-                           (size_t)S.d.n_frames * S.d.n_modes * FF * 8, hipMemcpyDeviceToDevice,
-                           c->stream));
+                           (size_t)S.d.n_frames * S.d.n_modes * NL * FF * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
   DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.P), probe_src, (size_t)S.d.n_modes * FF * 8,
                            hipMemcpyDeviceToDevice, c->stream));
   DM_HIP(c, hipMemcpyAsync(c->sat<float2>(0, S.L.O), object_src,
-                           (size_t)S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
+                           NL * S.d.obj_h * S.d.obj_w * 8, hipMemcpyDeviceToDevice,
                            c->stream));
   hipLaunchKernelGGL(dmk::k_mode_power, dim3((FF + 255) / 256), dim3(256), 0, c->stream,
                      c->sat<float2>(0, S.L.P), c->sat<float>(0, S.L.D), S.d.n_modes, (int)FF);
@@ -1437,7 +1533,7 @@ dm_status dm_autotune(dm_ctx* c, int32_t reps, const char* cache_path, dm_tuning
   for (int mp = DM_VIEWS_FUSED; mp <= DM_VIEWS_STREAMED_WIDE; ++mp) {
     if (c->bf16x3() && mp != DM_VIEWS_FUSED) continue;
     if (mp == DM_VIEWS_THREE_KERNEL && !have_spec) continue;
-    if (mp != DM_VIEWS_THREE_KERNEL && c->F > 128) continue;
+    if (mp != DM_VIEWS_THREE_KERNEL && (c->F > 128 || c->L > 1)) continue;
     for (int tile : {16, 32})
       for (int ch : chunk_opts) {
         dm_tuning t{tile, ch, mp, 0};

@@ -28,12 +28,13 @@ struct ScanDev {
   float2* psi;            // [N][M][F][F]
   const float* I;         // [N][F][F] (caller's)
   float2* P;              // [M][F][F]
-  float2* O;              // [H][W]
+  float2* O;              // [L][H][W] (L object modes; 1 on every path but
+                          // the three-kernel one)
   const int* pos;         // [N][2]
   const int* order;       // [N] views in spatial order
-  float2* opart;          // [N][F][F] per-view object numerators
+  float2* opart;          // [N][L][F][F] per-view object numerators
   float* gscr;            // [N][F][F] per-view modulus scale (fused path)
-  float2* tspec;          // [N][M][F][F] spectrum buffer (three-kernel path)
+  float2* tspec;          // [N][L M][F][F] spectrum buffer (three-kernel path)
   float* D;               // [F][F] mode power
   float2* num_part;       // [Cmax][M][F][F]
   float* den_part;        // [Cmax][F][F]
@@ -46,7 +47,8 @@ struct ScanDev {
   DevErrors* ring;        // [kRing]
   int N, H, W, tiles_x, ntiles, C, chunk, n_psi_parts;
   float beta;
-  int pad;
+  int L;                  // object modes; views hold the pairs (k, l) of
+                          // Eqs. 1-5 at mode index l * M + k
 };
 
 // ---------------------------------------------------------------------------
@@ -814,7 +816,9 @@ struct XCfg {
   static constexpr int XL_COL = 16 * (B + 1) + 2;
 };
 
-// (1) Z = 2 P O - psi and the DFT along rows, RB rows per block.
+// (1) Z = 2 P O - psi and the DFT along rows, RB rows per block.  M is the
+// number of probe modes; with L object modes a view holds L M frames, frame
+// c = l M + k being the pair of probe mode k and object mode l.
 template <int F>
 __global__ __launch_bounds__(256) void k_rows_fwd(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
@@ -823,10 +827,12 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
   constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_ROW;
   __shared__ float2 buf[RB * LD];
   const int t = threadIdx.x;
-  const int2 vm = vmap[blockIdx.x / M];
+  const int MT = M * scans[0].L;
+  const int2 vm = vmap[blockIdx.x / MT];
   const ScanDev& sc = scans[vm.x];
-  const int j = uni(vm.y), m = blockIdx.x % M;
-  const int jm = j * M + m;
+  const int j = uni(vm.y), mc = blockIdx.x % MT;
+  const int m = mc % M, l = mc / M;
+  const int jm = j * MT + mc;
   const float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
@@ -838,7 +844,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
   const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   const float2* __restrict__ pm = psi + (size_t)jm * FF + (size_t)row * F;
   const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
-  const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
+  const float2* __restrict__ Or = O + (size_t)l * uni(sc.H) * W + (size_t)(y0 + row) * W + x0;
   float2 a[16];
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) {
@@ -966,7 +972,10 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
 }
 
 // (3) inverse DFT along rows, psi' = psi + beta (Z' - P O), object numerator
-// of the view and eps_psi partial sums; all modes of RB rows per block.
+// of the view and eps_psi partial sums; all modes of RB rows per block.  With
+// L object modes the frames run l-major (c = l M + k) and the numerator of
+// object mode l, sum_k conj(P_k) psi'_{(k,l)}, is written after its M
+// frames.
 template <int F>
 __global__ __launch_bounds__(256) void k_rows_inv(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
@@ -992,13 +1001,16 @@ __global__ __launch_bounds__(256) void k_rows_inv(
   const int rl = t / B, n2 = t % B;
   const int row = blockIdx.y * RB + rl;
   const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
-  const float2* __restrict__ Or = O + (size_t)(y0 + row) * W + x0;
+  const int L = uni(sc.L), MT = M * L;
+  const size_t HW = (size_t)uni(sc.H) * W;
   float2 oacc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
   float e_d = 0.f, e_n = 0.f;
-  for (int m = 0; m < M; ++m) {
-    const size_t base = ((size_t)j * M + m) * FF + (size_t)row * F;
+  for (int mc = 0; mc < MT; ++mc) {
+    const int m = mc % M, l = mc / M;
+    const float2* __restrict__ Or = O + (size_t)l * HW + (size_t)(y0 + row) * W + x0;
+    const size_t base = ((size_t)j * MT + mc) * FF + (size_t)row * F;
     const float2* __restrict__ Tr = T + base;
     float2 a[16];
 #pragma unroll
@@ -1047,10 +1059,15 @@ __global__ __launch_bounds__(256) void k_rows_inv(
         oacc[n1] = cadd(oacc[n1], cmulc(pr[k], pn));
       }
     }
-  }
-  float2* __restrict__ oj = opart + (size_t)j * FF + (size_t)row * F;
+    if (m == M - 1) {
+      float2* __restrict__ oj = opart + ((size_t)j * L + l) * FF + (size_t)row * F;
 #pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) oj[B * n1 + n2] = oacc[n1];
+      for (int n1 = 0; n1 < 16; ++n1) {
+        oj[B * n1 + n2] = oacc[n1];
+        oacc[n1] = make_float2(0.f, 0.f);
+      }
+    }
+  }
   block_sum2<NT>(e_d, e_n, red);
   if (t == 0) {
     const int part = j * gridDim.y + blockIdx.y;
@@ -1068,7 +1085,9 @@ __global__ __launch_bounds__(256) void k_rows_inv(
 // (ascending), U at a time (8 for 16 x 16 tiles, 2 for 32 x 32), so G * U
 // views are in flight; the G partial
 // sums of each pixel are then added in group order through LDS.  The order of
-// every sum is fixed, so results are bitwise reproducible.
+// every sum is fixed, so results are bitwise reproducible.  blockIdx.y is the
+// object mode l (numerators opart[j][l], object O_l; the normaliser is the
+// same for every l).
 // ---------------------------------------------------------------------------
 template <int T, int G>
 __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ scans,
@@ -1083,9 +1102,10 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   const int2 tm = tmap[xcd_group_slot(blockIdx.x, gridDim.x)];
   const ScanDev& sc = scans[tm.x];
   const int tile = tm.y;
+  const int L = uni(sc.L), l = blockIdx.y;
   const float2* __restrict__ opart = sc.opart;
   const float* __restrict__ D = sc.D;
-  float2* __restrict__ O = sc.O;
+  float2* __restrict__ O = sc.O + (size_t)l * uni(sc.H) * uni(sc.W);
   const int* __restrict__ pos = sc.pos;
   const int* __restrict__ tile_ptr = sc.tile_ptr;
   const int* __restrict__ tile_views = sc.tile_views;
@@ -1111,7 +1131,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
       const int jv = tile_views[e + u * G];
       const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
       const int v = cx - xj;
-      const float2* __restrict__ oj = opart + (size_t)jv * FF;
+      const float2* __restrict__ oj = opart + ((size_t)jv * L + l) * FF;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const int uu = ry + RSTEP * k - yj;
@@ -1132,7 +1152,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
     const int jv = tile_views[e];
     const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
     const int v = cx - xj;
-    const float2* __restrict__ oj = opart + (size_t)jv * FF;
+    const float2* __restrict__ oj = opart + ((size_t)jv * L + l) * FF;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int uu = ry + RSTEP * k - yj;
@@ -1178,8 +1198,9 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   }
   block_sum2<256 * G>(e_d, e_n, red);
   if (threadIdx.x == 0) {
-    err_obj[2 * tile] = e_d;
-    err_obj[2 * tile + 1] = e_n;
+    const int part = l * uni(sc.ntiles) + tile;
+    err_obj[2 * part] = e_d;
+    err_obj[2 * part + 1] = e_n;
   }
 }
 
@@ -1187,7 +1208,9 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
 // Probe update (Eq. 4), stage 1: per chunk of views (consecutive in the
 // spatial view order) and block of 256 probe pixels,
 // sum_j conj(O'[win_j]) psi'_{j,k} for every mode and sum_j |O'[win_j]|^2.
-// Modes in groups of 8 held in registers; four views' loads in flight.
+// Modes in groups of 8 held in registers; four views' loads in flight.  With
+// L object modes both sums also run over l (views' frames l M + k), the
+// object modes in order inside each view.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict__ scans,
                                                        const int2* __restrict__ cmap, int M,
@@ -1204,6 +1227,8 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
   float2* __restrict__ num_part = sc.num_part;
   float* __restrict__ den_part = sc.den_part;
   const int N = sc.N, W = sc.W, chunk = sc.chunk;
+  const int L = sc.L, MT = M * L;
+  const size_t HW = (size_t)sc.H * W;
   if (pix >= FF) return;  // F * F need not fill the last block (no barriers here)
   const int j0 = cidx * chunk;
   const int j1 = min(N, j0 + chunk);
@@ -1216,7 +1241,9 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
     // kVU views per step, all of their loads issued before their use
     constexpr int kVU = 4;
     int i = j0;
-    for (; i + kVU <= j1; i += kVU) {
+    // one object mode: views kVU at a time; then (and with object modes
+    // throughout) view by view
+    for (; L == 1 && i + kVU <= j1; i += kVU) {
       float2 o[kVU], w[kVU][8];
 #pragma unroll
       for (int k = 0; k < kVU; ++k) {
@@ -1238,12 +1265,14 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
     for (; i < j1; ++i) {
       const int jv = order[i];
       const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
-      const float2 o = O[(size_t)(yj + u) * W + xj + v];
-      den += cabs2(o);
-      const float2* __restrict__ pj = psi + ((size_t)jv * M + mg) * FF + pix;
+      for (int l = 0; l < L; ++l) {
+        const float2 o = O[(size_t)l * HW + (size_t)(yj + u) * W + xj + v];
+        den += cabs2(o);
+        const float2* __restrict__ pj = psi + ((size_t)jv * MT + l * M + mg) * FF + pix;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (mg + q < M) acc[q] = cadd(acc[q], cmulc(o, pj[(size_t)q * FF]));
+        for (int q = 0; q < 8; ++q)
+          if (mg + q < M) acc[q] = cadd(acc[q], cmulc(o, pj[(size_t)q * FF]));
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q)
@@ -1327,6 +1356,13 @@ __device__ double block_sum_d(double x, double* red) {
   return r;
 }
 
+// sqrt(d / n) of two sums of squares; 0/0 is 0, d/0 infinite, and a NaN in
+// either sum stays NaN (so a diverged iteration is never reported as 0)
+__device__ __forceinline__ float rel_norm(double d, double n) {
+  if (isnan(d) || isnan(n)) return NAN;
+  return (n > 0) ? (float)sqrt(d / n) : (d > 0 ? INFINITY : 0.f);
+}
+
 // psi_valid = 0: this iteration's view kernel formed no eps_psi partials;
 // eps_psi is then reported as NaN and not taken for divergence.
 __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scans, int n_pblk,
@@ -1338,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scan
   const float* __restrict__ err_probe = sc.err_probe;
   int* __restrict__ counter = sc.counter;
   DevErrors* __restrict__ ring = sc.ring;
-  const int n_psi = sc.n_psi_parts, n_obj = sc.ntiles;
+  const int n_psi = sc.n_psi_parts, n_obj = sc.ntiles * sc.L;
   const int t = threadIdx.x;
   double v[4];
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -1360,16 +1396,15 @@ __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scan
     b = block_sum_d(b, red);
     pd_tot += a;
     pn_tot += b;
-    modes[m] = (b > 0) ? (float)sqrt(a / b) : (a > 0 ? INFINITY : 0.f);
+    modes[m] = rel_norm(a, b);
   }
   if (t == 0) {
     const int it = *counter;
     DevErrors e;
     e.iter = it + 1;
-    e.eps_psi = !psi_valid ? NAN
-                : (v[1] > 0) ? (float)sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.f);
-    e.eps_obj = (v[3] > 0) ? (float)sqrt(v[2] / v[3]) : (v[2] > 0 ? INFINITY : 0.f);
-    e.eps_probe = (pn_tot > 0) ? (float)sqrt(pd_tot / pn_tot) : (pd_tot > 0 ? INFINITY : 0.f);
+    e.eps_psi = !psi_valid ? NAN : rel_norm(v[0], v[1]);
+    e.eps_obj = rel_norm(v[2], v[3]);
+    e.eps_probe = rel_norm(pd_tot, pn_tot);
     bool bad = (psi_valid && !isfinite(e.eps_psi)) || !isfinite(e.eps_obj) ||
                !isfinite(e.eps_probe);
     for (int m = 0; m < 16; ++m) {
@@ -1385,19 +1420,23 @@ __global__ __launch_bounds__(256) void k_errors(const ScanDev* __restrict__ scan
 // ---------------------------------------------------------------------------
 // set-up kernels
 // ---------------------------------------------------------------------------
-// psi_{j,k} = P_k * O[window_j]; one block per (view, mode)
+// psi_{j,(k,l)} = P_k * O_l[window_j]; one block per (view, frame), frame
+// c = l M + k of the L M frames of a view (L object modes, O [L][H][W])
 __global__ __launch_bounds__(256) void k_init_psi(float2* __restrict__ psi,
                                                   const float2* __restrict__ P,
                                                   const float2* __restrict__ O,
                                                   const int* __restrict__ pos, int M, int F,
-                                                  int W) {
+                                                  int W, int L, int H) {
   const int jm = blockIdx.x;
-  const int j = jm / M, m = jm % M;
+  const int MT = M * L;
+  const int j = jm / MT, c = jm % MT;
+  const int m = c % M, l = c / M;
   const int FF = F * F;
   const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
+  const float2* __restrict__ Ol = O + (size_t)l * H * W;
   for (int p = threadIdx.x; p < FF; p += blockDim.x) {
     const int u = p / F, v = p % F;
-    psi[(size_t)jm * FF + p] = cmul(P[(size_t)m * FF + p], O[(size_t)(y0 + u) * W + x0 + v]);
+    psi[(size_t)jm * FF + p] = cmul(P[(size_t)m * FF + p], Ol[(size_t)(y0 + u) * W + x0 + v]);
   }
 }
 

@@ -31,7 +31,7 @@ DM_FLAG_MULTIPASS = 1   # force the three-kernel transform path (always for F = 
 DM_FLAG_PHASE_TIMING = 2  # HIP events around every phase launch
 DM_FLAG_GRAPH = 4         # capture one iteration into a hipGraph and replay it
 DM_FLAG_PSI_ERROR_LAST = 8  # eps_psi in the last iteration of a call only (psi-free update)
-DM_FLAG_PROBE_FIRST = 16  # probe update before the object update (Section III's swapped order)
+DM_FLAG_PROBE_FIRST = 16  # probe update before the object update (the order before Section III's swap)
 DM_VIEWS_FUSED = 0            # dm_tuning.view_path values
 DM_VIEWS_THREE_KERNEL = 1
 DM_VIEWS_STREAMED = 2
@@ -39,6 +39,8 @@ DM_VIEWS_STREAMED_CACHED = 3
 DM_VIEWS_STREAMED_MERGED = 4
 DM_VIEWS_STREAMED_WIDE = 5
 DM_MAX_MODES = 16
+DM_MAX_OBJ_MODES = 4
+DM_MAX_PAIRS = 32
 DM_MAX_PROBE_CHUNKS = 64
 PHASES = ["views", "object", "probe_partial", "probe_final", "errors"]
 
@@ -49,7 +51,7 @@ EXPORTED = [
     "dm_batch_workspace_bytes", "dm_batch_init", "dm_n_scans", "dm_scan_get_object",
     "dm_scan_get_probe", "dm_scan_error_history", "dm_get_tuning", "dm_set_tuning",
     "dm_autotune", "dm_warm_start", "dm_scan_warm_start", "dm_mode_power",
-    "dm_scan_mode_power",
+    "dm_scan_mode_power", "dm_orthogonalize_modes", "dm_scan_orthogonalize_modes",
 ]
 
 
@@ -57,7 +59,8 @@ class dm_desc(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int32), ("frame", ctypes.c_int32),
                 ("n_modes", ctypes.c_int32), ("obj_h", ctypes.c_int32),
                 ("obj_w", ctypes.c_int32), ("beta", ctypes.c_float),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("n_obj_modes", ctypes.c_int32)]
 
 
 class dm_errors(ctypes.Structure):
@@ -140,6 +143,10 @@ def lib():
     L.dm_mode_power.restype = i32
     L.dm_scan_mode_power.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.dm_scan_mode_power.restype = i32
+    L.dm_orthogonalize_modes.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.dm_orthogonalize_modes.restype = i32
+    L.dm_scan_orthogonalize_modes.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    L.dm_scan_orthogonalize_modes.restype = i32
     L.dm_get_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
     L.dm_get_tuning.restype = i32
     L.dm_set_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
@@ -161,9 +168,9 @@ def lib():
 
 
 def make_desc(n_frames, frame, n_modes, obj_h, obj_w, beta=0.8, precision=DM_FP32_FFT,
-              flags=0) -> dm_desc:
+              flags=0, n_obj_modes=0) -> dm_desc:
     return dm_desc(int(n_frames), int(frame), int(n_modes), int(obj_h), int(obj_w),
-                   float(beta), int(precision), int(flags))
+                   float(beta), int(precision), int(flags), int(n_obj_modes))
 
 
 def _ptr(t) -> Optional[int]:
@@ -249,6 +256,20 @@ def dm_mode_power(ctx, n_modes: int):
     arr = (ctypes.c_double * n_modes)()
     _check(lib().dm_mode_power(ctx, arr), ctx)
     return [float(arr[i]) for i in range(n_modes)]
+
+
+def dm_scan_orthogonalize_modes(ctx, scan: int, n_modes: int, want_power: bool = True):
+    """Orthogonal probe modes (the views mixed alike); the new modes' powers
+    (descending) if want_power, else None without synchronising."""
+    arr = (ctypes.c_double * n_modes)() if want_power else None
+    _check(lib().dm_scan_orthogonalize_modes(ctx, int(scan), arr), ctx)
+    return [float(arr[i]) for i in range(n_modes)] if want_power else None
+
+
+def dm_orthogonalize_modes(ctx, n_modes: int, want_power: bool = True):
+    arr = (ctypes.c_double * n_modes)() if want_power else None
+    _check(lib().dm_orthogonalize_modes(ctx, arr), ctx)
+    return [float(arr[i]) for i in range(n_modes)] if want_power else None
 
 
 def dm_iterations(ctx) -> int:
@@ -361,8 +382,10 @@ class DMContext:
             raise TypeError("I must be a float32 CUDA tensor [N][F][F]")
         n, f, f2 = I.shape
         m = probe0.shape[0]
-        h, w = object0.shape
-        self.desc = make_desc(n, f, m, h, w, beta, precision, flags)
+        # object [H][W], or [L][H][W] with L object modes
+        n_obj = object0.shape[0] if object0.dim() == 3 else 0
+        h, w = object0.shape[-2:]
+        self.desc = make_desc(n, f, m, h, w, beta, precision, flags, n_obj)
         nbytes = dm_workspace_bytes(self.desc)
         if nbytes == 0:
             raise DMError(DM_E_ARG, "invalid problem description")
@@ -377,6 +400,15 @@ class DMContext:
                            stream)
 
     @property
+    def n_obj_modes(self):
+        return max(1, self.desc.n_obj_modes)
+
+    def _obj_shape(self):
+        d = self.desc
+        return ((d.obj_h, d.obj_w) if d.n_obj_modes <= 1
+                else (d.n_obj_modes, d.obj_h, d.obj_w))
+
+    @property
     def n_modes(self):
         return self.desc.n_modes
 
@@ -385,8 +417,7 @@ class DMContext:
 
     def object(self):
         import torch
-        out = torch.empty((self.desc.obj_h, self.desc.obj_w), dtype=torch.complex64,
-                          device=self.device)
+        out = torch.empty(self._obj_shape(), dtype=torch.complex64, device=self.device)
         dm_get_object(self.ctx, out)
         return out
 
@@ -409,13 +440,18 @@ class DMContext:
         """sum over pixels of |P_k|^2 for every probe mode (synchronises)"""
         return dm_mode_power(self.ctx, self.n_modes)
 
+    def orthogonalize_modes(self, want_power: bool = True):
+        """eigenmodes of the probe modes' overlap matrix, views mixed alike;
+        returns their powers (descending) if want_power"""
+        return dm_orthogonalize_modes(self.ctx, self.n_modes, want_power)
+
     def state(self):
         import torch
         d = self.desc
-        psi = torch.empty((d.n_frames, d.n_modes, d.frame, d.frame), dtype=torch.complex64,
-                          device=self.device)
+        psi = torch.empty((d.n_frames, d.n_modes * self.n_obj_modes, d.frame, d.frame),
+                          dtype=torch.complex64, device=self.device)
         P = torch.empty((d.n_modes, d.frame, d.frame), dtype=torch.complex64, device=self.device)
-        O = torch.empty((d.obj_h, d.obj_w), dtype=torch.complex64, device=self.device)
+        O = torch.empty(self._obj_shape(), dtype=torch.complex64, device=self.device)
         it = dm_get_state(self.ctx, psi, P, O)
         return psi, P, O, it
 

@@ -61,6 +61,10 @@ def main():
     ap.add_argument("--traffic")
     ap.add_argument("--command", default="")
     ap.add_argument("--title", default="")
+    ap.add_argument("--view-kernels", default="",
+                    help="comma-separated kernel-name parts whose traffic is summed as one "
+                         "view update (the three-kernel path); default: the fused or "
+                         "streamed view kernel")
     ap.add_argument("--mfma", help="counter CSV with SQ_VALU_MFMA_BUSY_CYCLES, "
                     "GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_BF16")
     ap.add_argument("--simds", type=int, default=1024, help="SIMDs on the device")
@@ -96,11 +100,21 @@ def main():
                              f"{write[k] * 1024 * fw / 1e6:.1f} |")
         # the view kernel with the most dispatches (the merged paths run a
         # second form, with the eps_psi partials, once per dm_iterate call)
-        views = [k for k in fetch if VIEW_KERNEL in k]
-        vk = max(views, key=lambda k: counts[k]) if views else None
-        if vk:
-            traffic = {"read": fetch[vk] * 1024 * ff, "written": write[vk] * 1024 * fw}
-            traffic["total"] = traffic["read"] + traffic["written"]
+        if args.view_kernels:
+            parts = [p for p in args.view_kernels.split(",") if p]
+            ks = [k for k in fetch if any(p + "<" in k or k.endswith(p) for p in parts)]
+            vk = "views (3 kernels)" if ks else None
+            if ks:
+                traffic = {"read": sum(fetch[k] for k in ks) * 1024 * ff,
+                           "written": sum(write[k] for k in ks) * 1024 * fw}
+                traffic["total"] = traffic["read"] + traffic["written"]
+                traffic["kernels"] = ks
+        else:
+            views = [k for k in fetch if VIEW_KERNEL in k]
+            vk = max(views, key=lambda k: counts[k]) if views else None
+            if vk:
+                traffic = {"read": fetch[vk] * 1024 * ff, "written": write[vk] * 1024 * fw}
+                traffic["total"] = traffic["read"] + traffic["written"]
     if args.mfma:
         per = collections.defaultdict(lambda: collections.defaultdict(list))
         for r in csv.DictReader(open(args.mfma)):

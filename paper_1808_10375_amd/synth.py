@@ -35,6 +35,8 @@ import math
 from dataclasses import dataclass, field
 from typing import Optional
 
+import os
+
 import numpy as np
 
 try:  # multi-threaded FFT for generating large scans; numpy's as a fallback
@@ -233,13 +235,28 @@ def _windows(obj: np.ndarray, pos: np.ndarray, f: int) -> np.ndarray:
 
 def far_field_intensity(probes: np.ndarray, obj: np.ndarray, pos: np.ndarray,
                         chunk: int = 256) -> np.ndarray:
-    """I_j = sum_m |FFT2(P_m * O_window_j)|^2 (float64), computed in chunks."""
+    """I_j = sum_m |FFT2(P_m * O_window_j)|^2 (float64), computed in chunks;
+    with object modes obj [L][H][W], the sum also runs over l (Eq. 1)."""
+    if obj.ndim == 3:
+        return sum(far_field_intensity(probes, o, pos, chunk) for o in obj)
     f = probes.shape[-1]
     out = np.empty((len(pos), f, f), dtype=np.float64)
-    for s in range(0, len(pos), chunk):
+
+    def one(s):
         w = _windows(obj, pos[s:s + chunk], f)            # [c][F][F]
         ex = probes[None, :, :, :] * w[:, None, :, :]     # [c][M][F][F]
         out[s:s + chunk] = np.sum(np.abs(_fft2(ex)) ** 2, axis=1)
+
+    starts = range(0, len(pos), chunk)
+    if len(starts) < 4:
+        for s in starts:
+            one(s)
+    else:
+        # chunks are independent (each writes its own rows), so threads give
+        # the same array; numpy's FFT releases the interpreter lock
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex_pool:
+            list(ex_pool.map(one, starts))
     return out
 
 
@@ -445,13 +462,19 @@ def uneven_spirals_128(seed: int = 1000, n_scans: int = 16, sizes=None):
 # --------------------------------------------------------------------------
 def random_case(seed: int, n_frames: int, frame: int, n_modes: int,
                 obj_h: int, obj_w: int, consistent: bool = False,
-                beta: float = 0.8, perturb: Optional[float] = None) -> dict:
+                beta: float = 0.8, perturb: Optional[float] = None,
+                n_obj_modes: int = 1) -> dict:
     """A small random state (psi, P, O) with random positions and positive
     intensities.  With consistent=True the intensities and psi are exactly
     those of (P, O), i.e. a fixed point of the reconstruction.  With
     `perturb`, psi is the exit wave of (P, O) plus complex Gaussian noise of
     that relative size (a state near the physical one, whose overlap
-    updates are well conditioned)."""
+    updates are well conditioned).  With n_obj_modes = L > 1 the object is
+    [L][H][W] (mode l scaled by 0.6^l) and psi [N][L M][F][F], frame l M + k
+    holding the pair (probe mode k, object mode l)."""
+    if n_obj_modes > 1:
+        return _random_case_obj_modes(seed, n_frames, frame, n_modes, obj_h, obj_w,
+                                      consistent, beta, perturb, n_obj_modes)
     r = streams(seed)
     P = (r[0].standard_normal((n_modes, frame, frame))
          + 1j * r[0].standard_normal((n_modes, frame, frame)))
@@ -478,3 +501,30 @@ def random_case(seed: int, n_frames: int, frame: int, n_modes: int,
     return dict(psi=psi.astype(np.complex64), P=P.astype(np.complex64),
                 O=O.astype(np.complex64), I=I.astype(np.float32), pos=pos,
                 beta=beta)
+
+
+def _random_case_obj_modes(seed, n_frames, frame, n_modes, obj_h, obj_w, consistent,
+                           beta, perturb, L):
+    """random_case with L object modes (see there)."""
+    r = streams(seed + 7919 * L, 16)
+    base = random_case(seed, n_frames, frame, n_modes, obj_h, obj_w, beta=beta)
+    P = base["P"].astype(np.complex128)
+    pos = base["pos"]
+    O = np.stack([base["O"].astype(np.complex128)]
+                 + [0.6 ** l * grf_object(obj_h, obj_w, r[2 * l], r[2 * l + 1], sigma=1.5)
+                    for l in range(1, L)])
+    O = O.astype(np.complex64).astype(np.complex128)
+    ex = np.concatenate([P[None] * _windows(O[l], pos, frame)[:, None] for l in range(L)],
+                        axis=1)                                   # [N][L M][F][F]
+    I = far_field_intensity(P, O, pos)
+    if consistent:
+        psi = ex
+    elif perturb is not None:
+        noise = r[14].standard_normal(ex.shape) + 1j * r[14].standard_normal(ex.shape)
+        psi = ex + perturb * np.abs(ex) * noise
+        I = I * r[15].uniform(0.5, 1.5, size=I.shape)
+    else:
+        psi = r[14].standard_normal(ex.shape) + 1j * r[14].standard_normal(ex.shape)
+        I = I * r[15].uniform(0.5, 1.5, size=I.shape)
+    return dict(psi=psi.astype(np.complex64), P=P.astype(np.complex64),
+                O=O.astype(np.complex64), I=I.astype(np.float32), pos=pos, beta=beta)

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(dm.dm_desc) == 32
+    assert ctypes.sizeof(dm.dm_desc) == 36
     assert ctypes.sizeof(dm.dm_errors) == 80
     assert ctypes.sizeof(dm.dm_tuning) == 16
 
@@ -81,6 +81,25 @@ def test_workspace_bytes_valid_and_invalid():
     per_view = 2 * 128 * 128 * 8 + 128 * 128 * (8 + 4) + 2 * 4 + 4 + 4
     grown = dm.dm_workspace_bytes(desc(**more)) - dm.dm_workspace_bytes(desc(**many))
     assert 100 * per_view <= grown <= 100 * per_view + 64 * 1024
+
+
+def test_workspace_bytes_object_modes():
+    """L object modes: psi and the spectrum buffer hold L M frames per view,
+    the object L planes, and the view numerators L per view; L > 1 takes the
+    three-kernel path (spectrum buffer) at any power-of-two F."""
+    one = desc(frame=64, obj_h=200, obj_w=200, flags=dm.DM_FLAG_MULTIPASS)
+    two = desc(frame=64, obj_h=200, obj_w=200, n_obj_modes=2)
+    ff = 64 * 64
+    grown = dm.dm_workspace_bytes(two) - dm.dm_workspace_bytes(one)
+    expect = 2 * 10 * 2 * ff * 8 + 10 * ff * 8 + 200 * 200 * 8
+    assert expect <= grown <= expect + 128 * 1024, (grown, expect)
+    assert dm.dm_workspace_bytes(desc(n_obj_modes=1)) == dm.dm_workspace_bytes(desc())
+    for bad in (dict(n_obj_modes=-1), dict(n_obj_modes=5), dict(n_obj_modes=3, n_modes=11),
+                dict(n_obj_modes=2, frame=188, obj_h=300, obj_w=300),
+                dict(n_obj_modes=2, frame=128, obj_h=200, obj_w=200,
+                     precision=dm.DM_BF16X3_DFT)):
+        assert dm.dm_workspace_bytes(desc(**bad)) == 0, bad
+    assert dm.dm_workspace_bytes(desc(n_obj_modes=4, n_modes=8)) > 0
 
 
 def _init_status(d, pos, ws_bytes=None, ptrs=(256, 256, 256, 256)):

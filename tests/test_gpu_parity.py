@@ -284,7 +284,8 @@ def test_flyscan_256_strip_one_step():
                                                       (63, 11, 64, 2, 160, 150, 1),
                                                       (64, 7, 188, 2, 260, 260, None)])
 def test_one_step_probe_first_order(seed, n, f, m, h, w, view_path):
-    """Section III's swapped order (DM_FLAG_PROBE_FIRST): probe from the new
+    """Probe first (DM_FLAG_PROBE_FIRST, the order before Section III's
+    swap): probe from the new
     views and the old object, then object from the new views and the new
     probe, against the oracle in the same order."""
     say(f"case probe first seed={seed} N={n} F={f} M={m} obj={h}x{w} view_path={view_path}")

@@ -234,8 +234,8 @@ def test_dm_fixed_point_on_consistent_data(beta, probe_first):
 
 def test_update_orders_on_a_single_view():
     """One view, one mode: with the object updated first, O' = psi'/P on the
-    window and then P' = psi'/O' = P; with the probe first (Section III's
-    swapped order), P' = psi'/O and then O' = psi'/P' = O on the window,
+    window and then P' = psi'/O' = P; with the probe first (the order before
+    Section III's swap), P' = psi'/O and then O' = psi'/P' = O on the window,
     while pixels outside the window keep their value in both orders."""
     rng = np.random.default_rng(12)
     f = 6
@@ -403,3 +403,115 @@ def test_iteration_commutes_with_a_unitary_mode_mix():
     assert rel(b[0], np.einsum("ka,jkyx->jayx", V, a[0])) < 1e-12
     model = lambda PP: np.sum(np.abs(dm.dft2(dm.exit_waves(PP, O, pos))) ** 2, axis=1)  # noqa: E731
     assert rel(model(Q), model(P)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# object modes (Eqs. 1-5 with l running over L > 1 object modes): views hold
+# the pairs (k, l) at index l*M + k
+# ---------------------------------------------------------------------------
+def _pairs(P, O, pos):
+    """Exit waves of every pair written out view by view: [N][L*M][F][F]."""
+    f = P.shape[-1]
+    out = []
+    for (y, x) in pos:
+        out.append([P[k] * O[l, y:y + f, x:x + f]
+                    for l in range(O.shape[0]) for k in range(P.shape[0])])
+    return np.array(out)
+
+
+def test_object_modes_fixed_point_on_consistent_data():
+    """Consistent data with two object modes (I = sum over all pairs of
+    |F[P_k O_l]|^2, Eq. 1): one iteration leaves every quantity unchanged."""
+    rng = np.random.default_rng(41)
+    n, m, L, f, h, w = 6, 2, 2, 8, 20, 19
+    P = crand(rng, m, f, f)
+    O = np.stack([1 + 0.3 * crand(rng, h, w), 0.4 * crand(rng, h, w)])
+    pos = np.stack([rng.integers(0, h - f + 1, n), rng.integers(0, w - f + 1, n)], axis=1)
+    psi = _pairs(P, O, pos)
+    assert np.allclose(dm.exit_waves(P, O, pos), psi, rtol=0, atol=1e-14)
+    I = np.sum(np.abs(np.fft.fft2(psi)) ** 2, axis=1)
+    for probe_first in (False, True):
+        psi2, P2, O2, e = dm.iterate(psi, P, O, pos, I, 0.8, probe_first=probe_first)
+        den = dm.object_update(psi, P, O, pos)[1]
+        assert rel(psi2, psi) < 1e-12 and rel(P2, P) < 1e-12
+        assert rel(O2[:, den > 0], O[:, den > 0]) < 1e-12
+        assert e["eps_psi"] < 1e-12 and e["eps_obj"] < 1e-12 and e["eps_probe"] < 1e-12
+
+
+def test_object_modes_updates_are_least_squares():
+    """Eq. 5 per object mode and Eq. 4 summed over object modes minimise
+    sum_{j,k,l} ||psi_{j,(k,l)} - P_k O_l[window_j]||^2 over O (with P fixed)
+    and over P (with O fixed): dense lstsq solves built with explicit
+    indices."""
+    rng = np.random.default_rng(42)
+    n, m, L, f, h, w = 3, 2, 2, 4, 6, 7
+    P = crand(rng, m, f, f)
+    O = crand(rng, L, h, w)
+    psi = crand(rng, n, L * m, f, f)
+    pos = np.array([[0, 1], [2, 3], [1, 0]])
+    rows, rhs = [], []
+    for j in range(n):
+        for l in range(L):
+            for k in range(m):
+                for u in range(f):
+                    for v in range(f):
+                        row = np.zeros(L * h * w, dtype=np.complex128)
+                        row[(l * h + pos[j, 0] + u) * w + pos[j, 1] + v] = P[k, u, v]
+                        rows.append(row)
+                        rhs.append(psi[j, l * m + k, u, v])
+    sol = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0].reshape(L, h, w)
+    O_new, den = dm.object_update(psi, P, np.zeros((L, h, w), complex), pos)
+    cov = den > 0
+    assert O_new.shape == (L, h, w) and rel(O_new[:, cov], sol[:, cov]) < 1e-12
+    rows, rhs = [], []
+    for j in range(n):
+        for l in range(L):
+            for k in range(m):
+                for u in range(f):
+                    for v in range(f):
+                        row = np.zeros(m * f * f, dtype=np.complex128)
+                        row[(k * f + u) * f + v] = O[l, pos[j, 0] + u, pos[j, 1] + v]
+                        rows.append(row)
+                        rhs.append(psi[j, l * m + k, u, v])
+    sol = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0].reshape(m, f, f)
+    P_new, _ = dm.probe_update(psi, O, np.zeros((m, f, f), complex), pos)
+    assert rel(P_new, sol) < 1e-12
+
+
+def test_object_modes_reduce_to_one_mode_when_the_second_is_dark():
+    """An object mode that is zero, with zero views, contributes nothing to
+    the mode sum of F_c or to Eq. 4 and stays zero under Eq. 5: the first
+    mode's iteration equals the single-object iteration."""
+    c = synth.random_case(43, 7, 16, 2, 40, 36)
+    psi1 = c["psi"].astype(np.complex128)
+    P = c["P"].astype(np.complex128)
+    O1 = c["O"].astype(np.complex128)
+    I = c["I"].astype(np.float64)
+    ref = dm.iterate(psi1, P, O1, c["pos"], I, 0.8)
+    O2 = np.stack([O1, np.zeros_like(O1)])
+    psi2 = np.concatenate([psi1, np.zeros_like(psi1)], axis=1)
+    for probe_first in (False, True):
+        ref = dm.iterate(psi1, P, O1, c["pos"], I, 0.8, probe_first=probe_first)
+        out = dm.iterate(psi2, P, O2, c["pos"], I, 0.8, probe_first=probe_first)
+        assert rel(out[0][:, :2], ref[0]) < 1e-14 and np.all(out[0][:, 2:] == 0)
+        assert rel(out[1], ref[1]) < 1e-14
+        assert rel(out[2][0], ref[2]) < 1e-14 and np.all(out[2][1] == 0)
+
+
+def test_object_mode_swap_permutes_outputs():
+    """Relabelling the object modes permutes the views' pair blocks and the
+    object modes of the result, and changes nothing else."""
+    c = synth.random_case(44, 6, 16, 2, 40, 40, n_obj_modes=2)
+    psi = c["psi"].astype(np.complex128)
+    P, O = c["P"].astype(np.complex128), c["O"].astype(np.complex128)
+    I = c["I"].astype(np.float64)
+    a = dm.iterate(psi, P, O, c["pos"], I, 0.8)
+    psi_s = np.concatenate([psi[:, 2:], psi[:, :2]], axis=1)
+    b = dm.iterate(psi_s, P, O[::-1], c["pos"], I, 0.8)
+    assert rel(b[0], np.concatenate([a[0][:, 2:], a[0][:, :2]], axis=1)) < 1e-13
+    assert rel(b[1], a[1]) < 1e-13 and rel(b[2], a[2][::-1]) < 1e-13
+    # the generator's intensities are Eq. 1 over every pair
+    ex = _pairs(P, O, c["pos"])
+    I0 = np.sum(np.abs(np.fft.fft2(ex)) ** 2, axis=1)
+    r = I / I0
+    assert np.all((r > 0.5 - 1e-6) & (r < 1.5 + 1e-6))

@@ -342,6 +342,31 @@ dm_status dm_scan_mode_power(dm_ctx* ctx, int32_t scan, double* power_host);
 dm_status dm_orthogonalize_modes(dm_ctx* ctx, double* power_host);
 dm_status dm_scan_orthogonalize_modes(dm_ctx* ctx, int32_t scan, double* power_host);
 
+/* The same orthogonalisation without a context, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): it calls no allocator.  Its scratch (the
+ * overlap partial sums, V and the eigenvalues: 39,168 bytes) is a static
+ * device array that each GPU the library runs on holds until the process
+ * ends; the device address is looked up once per device.  Every call on a
+ * GPU shares that array, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race; calls on one stream are ordered.  The
+ * kernels overwrite all the scratch they read, so nothing carries over from
+ * an earlier call.  Same kernels, launch shapes and results as
+ * dm_orthogonalize_modes; it does not form the Eq. 5 mode power (no context).
+ *   probe_dev  complex64 [n_modes][frame][frame], device, mixed in place
+ *   psi_dev    complex64 [n_views][n_modes][frame][frame], device, mixed in
+ *              place; may be NULL when n_views = 0 (probe only)
+ *   power_dev  NULL, or device array of n_modes doubles: the eigenvalues
+ *              (the new modes' powers), descending
+ *   hip_stream hipStream_t of the current device (NULL: default stream)
+ * Enqueued on hip_stream; never synchronises.  The stream must belong to the
+ * current device.  DM_E_UNSUPPORTED: n_modes above 16 (the limit of the
+ * static scratch) or more than 2^31 pixels per frame; DM_E_ARG: other bad
+ * sizes or NULL/misaligned pointers; DM_E_HIP: a launch failed.  Messages
+ * through dm_last_error(NULL). */
+dm_status dm_orthogonalize_modes_noalloc(void* probe_dev, void* psi_dev, int32_t n_views,
+                                         int32_t n_modes, int32_t frame, double* power_dev,
+                                         void* hip_stream);
 
 /* ---- warm start ------------------------------------------------------------ */
 /* Replace the object with patches stitched by the object update (Section II,
@@ -382,7 +407,8 @@ void dm_free(dm_ctx* ctx);
 const char* dm_status_str(dm_status s);
 
 /* Last error message of a context ("" if none); valid until the next call
- * on it.  With NULL: the last message of a failed dm_init on this thread. */
+ * on it.  With NULL: the last message of a failed dm_init or context-free
+ * call (dm_orthogonalize_modes_noalloc) on this thread. */
 const char* dm_last_error(const dm_ctx* ctx);
 
 #ifdef __cplusplus

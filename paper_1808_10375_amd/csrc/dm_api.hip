@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1219,6 +1220,48 @@ dm_status time_tuning(dm_ctx* c, const dm_tuning& t, int reps, double* ms) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing
+// (dm_orthogonalize_modes_noalloc): a static device array, one copy per GPU
+// for the life of the process.  Its name is a host-side stand-in; the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[dmk::kOrthoScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices] = {};
+
+hipError_t scratch_address(void** out, std::string& why) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    why = "hipGetDevice";
+    return e;
+  }
+  if (dev < 0 || dev >= kScratchDevices) {
+    why = "device index beyond the scratch table";
+    return hipErrorInvalidDevice;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      why = "hipGetSymbolAddress(scratch)";
+      return e;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1329,6 +1372,46 @@ dm_status dm_scan_orthogonalize_modes(dm_ctx* c, int32_t scan, double* power_hos
 
 dm_status dm_orthogonalize_modes(dm_ctx* c, double* power_host) {
   return dm_scan_orthogonalize_modes(c, 0, power_host);
+}
+
+dm_status dm_orthogonalize_modes_noalloc(void* probe_dev, void* psi_dev, int32_t n_views,
+                                         int32_t n_modes, int32_t frame, double* power_dev,
+                                         void* hip_stream) {
+  g_init_error.clear();
+  if (n_modes > dmk::kOrthoMaxModes) {
+    g_init_error = "n_modes = " + std::to_string(n_modes) +
+                   " exceeds the 16 modes the static scratch holds";
+    return DM_E_UNSUPPORTED;
+  }
+  if (n_modes < 1 || frame < 1 || n_views < 0) {
+    g_init_error = "need n_modes >= 1, frame >= 1 and n_views >= 0";
+    return DM_E_ARG;
+  }
+  if ((double)frame * frame >= 2147483648.0 ||
+      (double)n_views * n_modes * frame * frame >= 9.2e18 / 8) {
+    g_init_error = "frame or view count too large";
+    return DM_E_UNSUPPORTED;
+  }
+  if (!probe_dev || !aligned8(probe_dev) || (n_views > 0 && (!psi_dev || !aligned8(psi_dev))) ||
+      (power_dev && !aligned8(power_dev))) {
+    g_init_error = "probe (and psi when n_views > 0) must be non-NULL 8-byte aligned device "
+                   "pointers, power_dev NULL or 8-byte aligned";
+    return DM_E_ARG;
+  }
+  void* scr = nullptr;
+  std::string why;
+  hipError_t e = scratch_address(&scr, why);
+  if (e == hipSuccess)
+    e = launch_ortho(reinterpret_cast<float2*>(probe_dev), reinterpret_cast<float2*>(psi_dev),
+                     n_views, n_modes, frame, scr, power_dev,
+                     reinterpret_cast<hipStream_t>(hip_stream));
+  else
+    why += ": ";
+  if (e != hipSuccess) {
+    g_init_error = why + hipGetErrorString(e);
+    return DM_E_HIP;
+  }
+  return DM_OK;
 }
 
 dm_status dm_scan_warm_start(dm_ctx* c, int32_t scan, const void* patches_dev) {
@@ -1589,7 +1672,7 @@ const char* dm_status_str(dm_status s) {
 }
 
 const char* dm_last_error(const dm_ctx* c) {
-  if (!c) return g_init_error.c_str();
+  if (!c) return g_init_error.c_str();  // dm_init and the context-free calls
   return c->err.c_str();
 }
 

@@ -52,6 +52,7 @@ EXPORTED = [
     "dm_scan_get_probe", "dm_scan_error_history", "dm_get_tuning", "dm_set_tuning",
     "dm_autotune", "dm_warm_start", "dm_scan_warm_start", "dm_mode_power",
     "dm_scan_mode_power", "dm_orthogonalize_modes", "dm_scan_orthogonalize_modes",
+    "dm_orthogonalize_modes_noalloc",
 ]
 
 
@@ -147,6 +148,8 @@ def lib():
     L.dm_orthogonalize_modes.restype = i32
     L.dm_scan_orthogonalize_modes.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.dm_scan_orthogonalize_modes.restype = i32
+    L.dm_orthogonalize_modes_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+    L.dm_orthogonalize_modes_noalloc.restype = i32
     L.dm_get_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
     L.dm_get_tuning.restype = i32
     L.dm_set_tuning.argtypes = [vp, ctypes.POINTER(dm_tuning)]
@@ -270,6 +273,16 @@ def dm_orthogonalize_modes(ctx, n_modes: int, want_power: bool = True):
     arr = (ctypes.c_double * n_modes)() if want_power else None
     _check(lib().dm_orthogonalize_modes(ctx, arr), ctx)
     return [float(arr[i]) for i in range(n_modes)] if want_power else None
+
+
+def dm_orthogonalize_modes_noalloc(probe, psi=None, power=None, stream=None):
+    """Context-free orthogonalisation on caller buffers (no allocation in the
+    library): probe [M][F][F] and psi [N][M][F][F] complex64 device tensors,
+    mixed in place; power: optional float64 device tensor [M]."""
+    m, f = int(probe.shape[0]), int(probe.shape[-1])
+    n = 0 if psi is None else int(psi.shape[0])
+    _check(lib().dm_orthogonalize_modes_noalloc(_ptr(probe), _ptr(psi), n, m, f, _ptr(power),
+                                                _stream_handle(stream)), None)
 
 
 def dm_iterations(ctx) -> int:

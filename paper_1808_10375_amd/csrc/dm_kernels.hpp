@@ -792,7 +792,11 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
 
 // ---------------------------------------------------------------------------
 // Multi-pass view update (any F = 16 B, used for F = 256): three kernels
-// around a spectrum buffer T [N][M][F][F].
+// around a spectrum buffer T [N][M][F][F] held k-major: after the DFT along
+// rows, element (row u, frequency l) of a frame sits at T[l][u], so every
+// line the column kernel transforms is contiguous; the row kernels transpose
+// their RB x F tiles through LDS and touch T along rows (RB consecutive
+// values of one line per run).
 // ---------------------------------------------------------------------------
 // rows per block of the row kernels: up to 256 threads, B threads per row
 template <int F>
@@ -867,19 +871,32 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 #pragma unroll
     for (int i = 0; i < NI; ++i) dftB<-1, B>(&a[i * B]);
   }
-  float2* __restrict__ Tr = T + (size_t)jm * FF + (size_t)row * F;
+  // the block's RB x F tile through LDS (row stride F + 1), then out along
+  // the k-major lines: thread (r, kg) stores T[l][row0 + r] for l = kg + B s
+  constexpr int LT = F + 1;
+  static_assert(LT <= LD, "the tile fits the exchange buffer");
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) Tr[(n2 + B * i) + 16 * k2] = a[i * B + k2];
+    for (int k2 = 0; k2 < B; ++k2) buf[rl * LT + (n2 + B * i) + 16 * k2] = a[i * B + k2];
+  __syncthreads();
+  const int r = t % RB, kg = t / RB;
+  float2* __restrict__ Tt = T + (size_t)jm * FF + (size_t)blockIdx.y * RB + r;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int l = kg + B * q;
+    Tt[(size_t)l * F] = buf[r * LT + l];
+  }
 }
 
 // (2) DFT along columns for CB columns of every mode of one view, the mode
 // sum, the modulus scale, and the inverse DFT along columns, in place in T.
-// Block = CB * B * M threads; dynamic LDS: CB * M lines of XL_COL complex.
-// One-dimensional grid of views x (F / CB) column blocks, mapped so that
-// each XCD takes runs of four neighbouring column blocks of one view: a
-// block's rows are CB * 8 bytes wide, so neighbours share cache lines.
+// Block = CB * B * M threads, B consecutive threads per line (each line a
+// contiguous run of the k-major buffer); dynamic LDS: CB * M lines of XL_COL
+// complex.  One-dimensional grid of views x (F / CB) column blocks, mapped
+// so that each XCD takes runs of four neighbouring column blocks of one
+// view (their reads of I share cache lines).
 template <int F>
 __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans,
                                                const int2* __restrict__ vmap,
@@ -896,15 +913,14 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
   float2* __restrict__ T = sc.tspec;
   const float* __restrict__ I = sc.I;
   const int col0 = (slot % nblk) * CB;
-  const int c = t % CB;
-  const int rest = t / CB;
-  const int n2 = rest % B;
-  const int m = rest / B;
+  const int n2 = t % B;
+  const int c = (t / B) % CB;
+  const int m = t / (B * CB);
   const int line = m * CB + c;
-  float2* __restrict__ Tm = T + ((size_t)j * M + m) * FF + col0 + c;
+  float2* __restrict__ Tm = T + ((size_t)j * M + m) * FF + (size_t)(col0 + c) * F;
   float2 a[16];
 #pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) a[n1] = Tm[(size_t)(B * n1 + n2) * F];
+  for (int n1 = 0; n1 < 16; ++n1) a[n1] = Tm[B * n1 + n2];
   dft16<-1>(a);
   if constexpr (B > 1) {
 #pragma unroll
@@ -968,7 +984,7 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
   }
   dft16<1>(a);
 #pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) Tm[(size_t)(B * n1 + n2) * F] = a[n1];
+  for (int n1 = 0; n1 < 16; ++n1) Tm[B * n1 + n2] = a[n1];
 }
 
 // (3) inverse DFT along rows, psi' = psi + beta (Z' - P O), object numerator
@@ -983,6 +999,8 @@ __global__ __launch_bounds__(256) void k_rows_inv(
   constexpr int B = F / 16, RB = RowCfg<F>::RB, FF = F * F, NI = 16 / B;
   constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_ROW;
   constexpr int NT = RowCfg<F>::NT;
+  constexpr int LT = F + 1;  // row stride of the transposed tile in buf
+  static_assert(LT <= LD, "the tile fits the exchange buffer");
   __shared__ float2 buf[RB * LD];
   __shared__ float red[2 * ((NT + 63) / 64)];
   const int t = threadIdx.x;
@@ -1011,12 +1029,25 @@ __global__ __launch_bounds__(256) void k_rows_inv(
     const int m = mc % M, l = mc / M;
     const float2* __restrict__ Or = O + (size_t)l * HW + (size_t)(y0 + row) * W + x0;
     const size_t base = ((size_t)j * MT + mc) * FF + (size_t)row * F;
-    const float2* __restrict__ Tr = T + base;
+    // the block's RB x F tile, read along the k-major lines (thread (r, kg)
+    // loads T[l][row0 + r] for l = kg + B s) and transposed through LDS
+    {
+      const int r = t % RB, kg = t / RB;
+      const float2* __restrict__ Tt =
+          T + ((size_t)j * MT + mc) * FF + (size_t)blockIdx.y * RB + r;
+      float2 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = Tt[(size_t)(kg + B * q) * F];
+      __syncthreads();  // the previous mode's reads of buf are done
+#pragma unroll
+      for (int q = 0; q < 16; ++q) buf[r * LT + kg + B * q] = v[q];
+      __syncthreads();
+    }
     float2 a[16];
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) a[i * B + k2] = Tr[(n2 + B * i) + 16 * k2];
+      for (int k2 = 0; k2 < B; ++k2) a[i * B + k2] = buf[rl * LT + (n2 + B * i) + 16 * k2];
     if constexpr (B > 1) {
 #pragma unroll
       for (int i = 0; i < NI; ++i) dftB<1, B>(&a[i * B]);

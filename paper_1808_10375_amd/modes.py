@@ -3,9 +3,13 @@
 first run in which some mode carries less than 1% of the total intensity;
 the count before it is kept.
 
-The per-mode powers come from the library (`dm_mode_power`: sums over
-pixels of |P_k|^2 on the device); this module holds only the host-side
-bookkeeping of the search.
+The per-mode powers come from the library: best the eigen-powers of
+`dm_orthogonalize_modes` (the eigenvalues of the modes' overlap matrix, which
+a unitary mix of the modes leaves alone; the mix does not change the
+intensity model of Eq. 1, so the plain powers of non-orthogonal modes,
+`dm_mode_power`, depend on how a reconstruction happened to split the
+power between them).  This module holds only the host-side bookkeeping of
+the search.
 """
 from __future__ import annotations
 
@@ -24,7 +28,8 @@ def choose_mode_count(run: Callable[[int], Sequence[float]], max_modes: int,
                       threshold: float = 0.01,
                       start: int = 1) -> Tuple[int, List[Tuple[int, List[float]]]]:
     """run(M) reconstructs with M probe modes and returns the M mode powers
-    (for example a DMContext's `mode_power()` after some iterations).  M runs
+    (for example a DMContext's `orthogonalize_modes()` after some
+    iterations).  M runs
     from `start` up to `max_modes`; the search stops at the first M whose
     smallest share is below `threshold` and returns the M before it (or
     `start`), with the shares of every trial run."""

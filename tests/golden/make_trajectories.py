@@ -11,7 +11,10 @@ which the GPU's trajectory is judged).  Cases:
 
 Beside the error curves and the final probe and object it stores how far
 the perturbed run ends from the base run: in the probe, in the object
-(weighted by the Eq. 5 denominator) and in the modelled intensities
+(weighted by the Eq. 5 denominator), both also without the ambiguities (the
+object after the best complex scale, the probe through its mode-summed
+power, which a unitary mix of the modes leaves alone), and in the modelled
+intensities
 sum_k |F[P_k O_j]|^2 of every view, which, unlike P and O, are free of the
 ambiguities of the problem (a complex scale c with P -> cP, O -> O/c, and a
 linear phase ramp moved between probe and object).
@@ -78,6 +81,24 @@ def modelled_intensity(P, O, pos):
     return np.sum(np.abs(oracle.dft2(oracle.exit_waves(P, O, pos))) ** 2, axis=1)
 
 
+def aligned_distances(P, O, P_ref, O_ref, w):
+    """How far (P, O) lies from (P_ref, O_ref) once the ambiguities of
+    Eqs. 1-5 are removed.  The exit waves P_k O are unchanged by a complex
+    scale (P, O) -> (P / c, c O) and the intensities of Eq. 1 by a unitary
+    mix of the probe modes; so O is compared after the scale c that brings
+    it closest to O_ref (least squares weighted by w, the Eq. 5
+    denominator), and the probe through its mode-summed power
+    sum_k |P_k / c|^2, which no mix changes.  O and O_ref cover the same
+    box of pixels as w.  Returns (probe power distance, weighted object
+    distance), both relative L2."""
+    c = np.sum(w * np.conj(O) * O_ref) / np.sum(w * np.abs(O) ** 2)
+    d_O = float(np.sqrt(np.sum(w * np.abs(c * O - O_ref) ** 2) / np.sum(w * np.abs(O_ref) ** 2)))
+    pw = np.sum(np.abs(P / c) ** 2, axis=0)
+    pw_ref = np.sum(np.abs(P_ref) ** 2, axis=0)
+    d_P = float(np.linalg.norm(pw - pw_ref) / np.linalg.norm(pw_ref))
+    return d_P, d_O
+
+
 def make(case):
     s = CASES[case]()
     print("oracle run from the cold start", flush=True)
@@ -94,14 +115,16 @@ def make(case):
 
     out = out_path(case)
     model_spread = rel(modelled_intensity(Pp, Op, s.pos), modelled_intensity(P, O, s.pos))
+    sP, sO = aligned_distances(Pp, Op[y0:y1, x0:x1], P, O[y0:y1, x0:x1], w)
     np.savez_compressed(
         out, eps=h, eps_perturbed=hp, P=P.astype(np.complex64),
         O_box=O[y0:y1, x0:x1].astype(np.complex64), den_box=w.astype(np.float32),
         box=np.array([y0, y1, x0, x1]), perturb=PERTURB,
         P_spread=rel(Pp, P), O_spread_weighted=rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w),
-        model_spread=model_spread)
+        P_spread_aligned=sP, O_spread_aligned=sO, model_spread=model_spread)
     print(f"wrote {out}: eps_P(50) {h[49, 0]:.4e} eps_P(100) {h[99, 0]:.4e}; "
           f"spread P {rel(Pp, P):.3e} O(weighted) {rel(Op[y0:y1, x0:x1], O[y0:y1, x0:x1], w):.3e} "
+          f"without the ambiguities: probe power {sP:.3e} O(weighted) {sO:.3e}; "
           f"modelled intensities {model_spread:.3e}",
           flush=True)
 

@@ -12,8 +12,9 @@ itself under that perturbation.  Final probe and object are compared through
 what the problem fixes uniquely -- the modelled intensities
 sum_k |F[P_k O_j]|^2 of every view (Eq. 1) -- since P and O themselves drift
 along the ambiguities of the problem (a complex scale, a phase ramp moved
-between probe and object); P and the weighted O are compared against the
-oracle's spread as well.
+between probe and object, a unitary mix of the probe modes); the weighted O
+after its best complex scale and the probe's mode-summed power are compared
+against the oracle's spread as well.
 """
 import importlib.util
 import os
@@ -79,16 +80,24 @@ def test_trajectory_tracks_the_oracle_over_100_iterations(case):
     m_g = model(P_g.astype(np.complex128), O_g.astype(np.complex128), s.pos)
     m_o = model(P_o.astype(np.complex128), O_o, s.pos)
     r_model = rel(m_g, m_o)
-    r_P = rel(P_g, P_o)
-    r_O = rel(O_g[y0:y1, x0:x1], O_box, w)
+    # P and O without the ambiguities along which both the GPU's and the
+    # oracle's runs drift (a complex scale between P and O, a unitary mix of
+    # the probe modes): the object after its best complex scale, the probe
+    # through its mode-summed power
+    r_P, r_O = golden.aligned_distances(P_g.astype(np.complex128),
+                                        O_g[y0:y1, x0:x1].astype(np.complex128),
+                                        P_o.astype(np.complex128),
+                                        O_box.astype(np.complex128), w)
     say(f"  err(1) oracle {eo[0]:.5e} gpu {eg[0]:.5e}; err(50) {eo[49]:.4e}/{eg[49]:.4e}; "
         f"err(100) {eo[-1]:.4e}/{eg[-1]:.4e}")
     say(f"  deviation gpu: median {np.median(dg):.2e} p90 {np.percentile(dg, 90):.2e} "
         f"max ratio {rg:.3f}; oracle under 6e-8 noise: median {np.median(dp):.2e} "
         f"p90 {np.percentile(dp, 90):.2e} max ratio {rp:.3f}")
     say(f"  final state vs oracle: modelled intensities {r_model:.2e} (oracle spread "
-        f"{float(g['model_spread']):.2e}), P {r_P:.2e} (spread {float(g['P_spread']):.2e}), "
-        f"O weighted {r_O:.2e} (spread {float(g['O_spread_weighted']):.2e})")
+        f"{float(g['model_spread']):.2e}); without the ambiguities: probe power {r_P:.2e} "
+        f"(spread {float(g['P_spread_aligned']):.2e}), O weighted {r_O:.2e} (spread "
+        f"{float(g['O_spread_aligned']):.2e}); with them: P {rel(P_g, P_o):.2e} "
+        f"(spread {float(g['P_spread']):.2e})")
     say(f"  err rises after iteration 50: oracle {eo[-1] > eo[49]}, gpu {eg[-1] > eg[49]}")
     # the first step starts from identical states
     assert abs(eg[0] - eo[0]) <= 1e-4 * eo[0]
@@ -97,5 +106,12 @@ def test_trajectory_tracks_the_oracle_over_100_iterations(case):
     assert rg <= max(1.5 * rp, 1.2)
     assert abs(eg[-1] - eo[-1]) <= 0.1 * eo[-1]
     assert r_model <= max(2 * float(g["model_spread"]), 1e-4)
-    assert r_P <= max(2 * float(g["P_spread"]), 1e-3)
-    assert r_O <= max(2 * float(g["O_spread_weighted"]), 1e-3)
+    # P and O themselves only where the oracle's own final state is
+    # reproducible (its perturbed run ends within 10% of it); where it is
+    # not, the data and the iteration leave them undetermined (the modelled
+    # intensities above are what the computation fixes)
+    if float(g["O_spread_aligned"]) < 0.1 and float(g["P_spread_aligned"]) < 0.1:
+        assert r_P <= max(2 * float(g["P_spread_aligned"]), 1e-3)
+        assert r_O <= max(2 * float(g["O_spread_aligned"]), 1e-3)
+    if float(g["P_spread"]) < 0.1:
+        assert rel(P_g, P_o) <= max(2 * float(g["P_spread"]), 1e-3)

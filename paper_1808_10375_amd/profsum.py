@@ -67,6 +67,9 @@ def main():
                          "streamed view kernel")
     ap.add_argument("--mfma", help="counter CSV with SQ_VALU_MFMA_BUSY_CYCLES, "
                     "GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_BF16")
+    ap.add_argument("--stalls", help="counter CSV with SQ_WAVE_CYCLES, SQ_WAIT_ANY, "
+                    "SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_VALU/LDS/VMEM, SQ_LDS_BANK_CONFLICT, "
+                    "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
     ap.add_argument("--simds", type=int, default=1024, help="SIMDs on the device")
     ap.add_argument("--xcds", type=int, default=8,
                     help="GRBM_GUI_ACTIVE instances summed in the CSV (one per XCD)")
@@ -132,6 +135,28 @@ def main():
             util = 100.0 * m["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * args.simds)
             lines.append(f"| `{k}` | {util:.1f} | "
                          f"{m['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512 / 1e9:.1f} | {cyc:.3g} |")
+    if args.stalls:
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(args.stalls)):
+            per[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        lines += ["", "Where the waves' time goes, per dispatch (each SQ_* count over "
+                  "SQ_WAVE_CYCLES, the summed lifetime of the kernel's waves; MFMA busy = "
+                  "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x "
+                  f"{args.simds} SIMDs)):", "",
+                  "| kernel | waiting on memory/LDS (SQ_WAIT_ANY) | waiting to issue "
+                  "(SQ_WAIT_INST_ANY) | issuing VALU | issuing LDS | LDS bank conflicts | "
+                  "MFMA busy % |", "|---|---:|---:|---:|---:|---:|---:|"]
+        for k, d in per.items():
+            m = {c: sum(v) / len(v) for c, v in d.items()}
+            wc = m.get("SQ_WAVE_CYCLES", 0)
+            if wc < 1e8:
+                continue
+            mf = ""
+            if m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) > 0 and m.get("GRBM_GUI_ACTIVE", 0) > 0:
+                mf = f"{100 * m['SQ_VALU_MFMA_BUSY_CYCLES'] / (m['GRBM_GUI_ACTIVE'] / args.xcds * args.simds):.1f}"
+            lines.append(f"| `{k}` | {m['SQ_WAIT_ANY'] / wc:.2f} | {m['SQ_WAIT_INST_ANY'] / wc:.2f} | "
+                         f"{m['SQ_ACTIVE_INST_VALU'] / wc:.3f} | {m['SQ_ACTIVE_INST_LDS'] / wc:.3f} | "
+                         f"{m['SQ_LDS_BANK_CONFLICT'] / wc:.3f} | {mf} |")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")

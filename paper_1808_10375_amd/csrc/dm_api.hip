@@ -191,7 +191,7 @@ ScanLayout scan_layout(const dm_desc& d) {
   L.pos = take(N * 2 * 4);
   L.order = take(N * 4);
   L.tile_ptr = take(((size_t)L.ntiles16 + 1) * 4);
-  L.tile_views = take((size_t)L.nnz16 * sizeof(int4));
+  L.tile_views = take((size_t)L.nnz16 * 4);
   L.bytes = off;
   return L;
 }
@@ -441,9 +441,9 @@ std::vector<float2> twiddles(int F) {
 }
 
 // Lists of views whose window meets each T x T object tile, ascending view
-// order; each entry holds the view and its window corner (view, y, x, 0).
+// order.
 void build_tile_lists(const dm_desc& d, int T, const std::vector<int>& pos,
-                      std::vector<int>& ptr, std::vector<int4>& views) {
+                      std::vector<int>& ptr, std::vector<int>& views) {
   const int F = d.frame;
   const int tx_n = (d.obj_w + T - 1) / T, ty_n = (d.obj_h + T - 1) / T;
   const int ntiles = tx_n * ty_n;
@@ -455,13 +455,12 @@ void build_tile_lists(const dm_desc& d, int T, const std::vector<int>& pos,
   }
   ptr.assign(ntiles + 1, 0);
   for (int i = 0; i < ntiles; ++i) ptr[i + 1] = ptr[i] + count[i];
-  views.assign(std::max(ptr[ntiles], 1), make_int4(0, 0, 0, 0));
+  views.assign(std::max(ptr[ntiles], 1), 0);
   std::vector<int> fill(ptr.begin(), ptr.end() - 1);
   for (int j = 0; j < d.n_frames; ++j) {
     const int y = pos[2 * j], x = pos[2 * j + 1];
     for (int ty = y / T; ty <= (y + F - 1) / T; ++ty)
-      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx)
-        views[fill[ty * tx_n + tx]++] = make_int4(j, y, x, 0);
+      for (int tx = x / T; tx <= (x + F - 1) / T; ++tx) views[fill[ty * tx_n + tx]++] = j;
   }
 }
 
@@ -511,8 +510,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
   std::vector<ScanDev> sd(n);
   std::vector<int2> tmap, cmap;
   // host staging that must outlive the asynchronous copies below
-  std::vector<std::vector<int>> ptrs(n);
-  std::vector<std::vector<int4>> lists(n);
+  std::vector<std::vector<int>> ptrs(n), lists(n);
   for (int s = 0; s < n; ++s) {
     auto& S = c->scans[s];
     const ScanLayout& L = S.L;
@@ -528,8 +526,8 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
     S.C = (S.d.n_frames + S.chunk - 1) / S.chunk;  // no empty chunks
     DM_HIP(c, hipMemcpyAsync(c->sat<int>(s, L.tile_ptr), ptrs[s].data(),
                              ptrs[s].size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    DM_HIP(c, hipMemcpyAsync(c->sat<int4>(s, L.tile_views), lists[s].data(),
-                             lists[s].size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+    DM_HIP(c, hipMemcpyAsync(c->sat<int>(s, L.tile_views), lists[s].data(),
+                             lists[s].size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     ScanDev& v = sd[s];
     v.psi = c->sat<float2>(s, L.psi);
     v.I = S.I;
@@ -547,7 +545,7 @@ dm_status apply_tuning(dm_ctx* c, const dm_tuning& t) {
     v.err_obj = c->sat<float>(s, L.err_obj);
     v.err_probe = c->sat<float>(s, L.err_probe);
     v.tile_ptr = c->sat<int>(s, L.tile_ptr);
-    v.tile_views = c->sat<int4>(s, L.tile_views);
+    v.tile_views = c->sat<int>(s, L.tile_views);
     v.counter = c->sat<int>(s, L.counter);
     v.ring = c->sat<DevErrors>(s, L.ring);
     v.N = S.d.n_frames;

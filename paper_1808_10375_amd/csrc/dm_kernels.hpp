@@ -42,7 +42,7 @@ struct ScanDev {
   float* err_obj;         // [ntiles_max][2]
   float* err_probe;       // [n_pblk][M][2]
   const int* tile_ptr;    // [ntiles + 1]
-  const int4* tile_views; // [nnz] (view, y, x, 0) of each view meeting a tile
+  const int* tile_views;  // [nnz]
   int* counter;           // iteration counter of this scan
   DevErrors* ring;        // [kRing]
   int N, H, W, tiles_x, ntiles, C, chunk, n_psi_parts;
@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   float2* __restrict__ O = sc.O + (size_t)l * uni(sc.H) * uni(sc.W);
   const int* __restrict__ pos = sc.pos;
   const int* __restrict__ tile_ptr = sc.tile_ptr;
-  const int4* __restrict__ tile_views = sc.tile_views;
+  const int* __restrict__ tile_views = sc.tile_views;
   float* __restrict__ err_obj = sc.err_obj;
   const int H = uni(sc.H), W = uni(sc.W), tiles_x = uni(sc.tiles_x);
   const int ty = tile / tiles_x, tx = tile % tiles_x;
@@ -1152,17 +1152,15 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   for (int k = 0; k < PPT; ++k) { num[k] = make_float2(0.f, 0.f); den[k] = 0.0; }
   const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
   const size_t FF = (size_t)F * F;
-  constexpr int U = (16 / PPT > 2) ? 16 / PPT : 2;  // views per group in flight
+  constexpr int U = (8 / PPT > 2) ? 8 / PPT : 2;  // views per group in flight
   int e = e0 + q;
   for (; e + (U - 1) * G < e1; e += U * G) {
     float2 vv[U][PPT];
     float dd[U][PPT];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      // one load gives the view and its corner, so each view's numerator
-      // loads wait on one round trip, not on two dependent index loads
-      const int4 en = tile_views[e + u * G];
-      const int jv = en.x, yj = en.y, xj = en.z;
+      const int jv = tile_views[e + u * G];
+      const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
       const int v = cx - xj;
       const float2* __restrict__ oj = opart + ((size_t)jv * L + l) * FF;
 #pragma unroll
@@ -1182,8 +1180,8 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
       }
   }
   for (; e < e1; e += G) {
-    const int4 en = tile_views[e];
-    const int jv = en.x, yj = en.y, xj = en.z;
+    const int jv = tile_views[e];
+    const int yj = pos[2 * jv], xj = pos[2 * jv + 1];
     const int v = cx - xj;
     const float2* __restrict__ oj = opart + ((size_t)jv * L + l) * FF;
 #pragma unroll

@@ -78,10 +78,7 @@ def test_workspace_bytes_valid_and_invalid():
     assert abs(got - expect) <= 4096, (got, expect)
     many = dict(frame=128, obj_h=200, obj_w=200, n_frames=600)
     more = dict(many, n_frames=700)
-    # psi, the object numerator and scale, positions and order, and the
-    # object-tile entries (view, y, x, 0) of the (128/16 + 1)^2 tiles a
-    # window can meet
-    per_view = 2 * 128 * 128 * 8 + 128 * 128 * (8 + 4) + 2 * 4 + 4 + 4 + 81 * 16
+    per_view = 2 * 128 * 128 * 8 + 128 * 128 * (8 + 4) + 2 * 4 + 4 + 4
     grown = dm.dm_workspace_bytes(desc(**more)) - dm.dm_workspace_bytes(desc(**many))
     assert 100 * per_view <= grown <= 100 * per_view + 64 * 1024
 

@@ -33,10 +33,12 @@ ORACLE_ERR_FILE = os.path.join(ROOT, "tests", "golden", "spiral_2500_err.json")
 
 
 def kernel_hash() -> str:
-    """Hash of every library source (kernels and the launch code that picks
-    their shapes): a committed traffic figure is used only while it matches."""
+    """Hash of every library source of the DM iteration (kernels and the
+    launch code that picks their shapes; the warm-start network's dmnet_*
+    files are left out): a committed traffic figure is used only while it
+    matches."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in sorted(n for n in os.listdir(CSRC) if not n.startswith("dmnet")):
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())

@@ -208,16 +208,23 @@ def copy_calibration(reps: int = 3):
     print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
-def bench_batched(steps: int, warmup: int, conv_iters: int):
-    """16 scans of uneven size (200-3000 views, 3 modes, 128x128 frames,
-    1024x1024 objects) advanced together: one hipGraph launch per iteration,
-    launch shapes from the autotuner."""
-    import torch
-    from paper_1808_10375_amd import dm, synth
+def uneven_scans():
+    from paper_1808_10375_amd import synth
     t0 = time.time()
     scans = synth.uneven_spirals_128(1000)
     print(f"# generated 16 uneven scans in {time.time() - t0:.1f} s", file=sys.stderr,
           flush=True)
+    return scans
+
+
+def bench_batched(steps: int, warmup: int, conv_iters: int, scans=None):
+    """16 scans of uneven size (200-3000 views, 3 modes, 128x128 frames,
+    1024x1024 objects) advanced together: one hipGraph launch per iteration,
+    launch shapes from the autotuner."""
+    import torch
+    from paper_1808_10375_amd import dm
+    if scans is None:
+        scans = uneven_scans()
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     sizes = [sc.n_frames for sc in scans]
@@ -251,6 +258,56 @@ def bench_batched(steps: int, warmup: int, conv_iters: int):
             / HBM_PEAK_GBS,
             "err_after_%d" % n_it: {"min": min(final), "median": float(np.median(final)),
                                     "max": max(final)}}
+
+
+def bench_warm_start(scans, ms_per_iter: float, n_iter: int = 100, train_scans: int = 128,
+                     epochs: int = 8):
+    """The learned warm start on the 16 uneven scans: the network is trained
+    here (pairs from `train_scans` synthetic scans of the same family, each
+    binned frame against the true object under its window, masked to the
+    probe's footprint), then every scan runs n_iter iterations from the flat
+    object (cold) and from the stitched predictions (warm), same initial
+    probe.  err <= 1e-3 is out of reach of Poisson data, so the level is 1.1 x
+    the cold run's err after n_iter iterations (no FP64 reference exists for
+    these 28,031 views); time to it = the warm start's inference and stitch
+    time + iterations x the batched form's time per iteration."""
+    import torch
+    from paper_1808_10375_amd import warmstart as ws
+    from paper_1808_10375_amd.dmnet import DMNet
+    dev = "cuda:0"
+    t0 = time.time()
+    net = DMNet(32, size=64, base_ch=32, levels=4, lr=1e-3, device=dev)
+    net.set_params(ws.initial_params(10000))
+    x, t = ws.make_pairs(list(range(10000, 10000 + train_scans)), net=net, device=dev)
+    xv, tv = ws.make_pairs(list(range(20000, 20004)), net=net, device=dev)
+    t_pairs = time.time() - t0
+    flat = torch.zeros_like(tv)
+    flat[:, 0] = 1.0
+    flat_loss = float(torch.mean((flat - tv) ** 2))
+    hist, steps, t_train = ws.train(net, x, t, xv, tv, epochs, 32, log_every=10 ** 9)
+    n_pairs = int(x.shape[0])
+    del x, t
+    rep = ws.compare(net, scans, n_iter, 32, dev, checkpoints=(1, 10))
+    net.free()
+    fin = rep["iters_to_1.1x_final"]
+    med = {f: fin["median"][f] for f in ("cold", "warm")}
+    return {
+        "workload": "the 16 uneven scans of the batched form",
+        "network": {"levels": 4, "channels": [32, 64, 128, 256], "params": net.n_params},
+        "training": {"pairs": n_pairs, "scans": train_scans, "epochs": epochs, "steps": steps,
+                     "pairs_s": t_pairs, "train_s": t_train,
+                     "val_loss": hist[-1]["val_loss"], "val_loss_flat_object": flat_loss},
+        "inference_and_stitch_s": rep["warm_init_s"],
+        "level": "1.1 x the cold run's err after %d iterations, per scan" % n_iter,
+        "iters_to_level_median": med,
+        "seconds_to_level_median": {
+            "cold": med["cold"] * ms_per_iter * 1e-3,
+            "warm": rep["warm_init_s"] + med["warm"] * ms_per_iter * 1e-3},
+        "iters_saved_per_scan": fin["saved_per_scan"],
+        "iters_to_fixed_levels": rep["median"]["iters_to"],
+        "err_at_median": rep["median"]["err_at"],
+        "object_error_median": rep["median_object_error"],
+    }
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -441,6 +498,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched-scans (and other forms') measurements")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the warm-start form (it trains its network, about a minute)")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="transform form of the headline run (bf16x3: F = 128 only)")
     ap.add_argument("--psi-error-last", action="store_true",
@@ -577,11 +636,17 @@ def main():
         out["dtype"] = "bf16x3/f32"
     if (not args.no_forms and args.config == 1 and not args.paper_frame
             and not args.paper_weak and args.precision == "fp32"):
+        scans = uneven_scans()
         out["forms"] = {"psi_error_last": bench_psi_error_last(scan, args.steps, args.warmup),
                         "probe_first": bench_probe_first(scan, args.steps, args.warmup),
-                        "batched": bench_batched(args.steps, args.warmup, args.conv_iters),
+                        "batched": bench_batched(args.steps, args.warmup, args.conv_iters,
+                                                 scans),
                         "bf16x3": bench_bf16x3(scan, args.steps, args.warmup, args.conv_iters,
                                                errs[-1], ofe)}
+        if not args.no_warm:
+            print("# warm start: training the network", file=sys.stderr, flush=True)
+            out["forms"]["warm_start"] = bench_warm_start(
+                scans, out["forms"]["batched"]["ms_per_step"])
         pf = out["forms"]["probe_first"]
         # Section III: swapping to object first and overlapping each batch's
         # object embedding with the next batch's view update gave the paper

@@ -10,8 +10,8 @@
  * fallback and the reference the warm start is measured against.
  *
  * Network (U-Net style encoder-decoder, NCHW float32 activations):
- *   input   [n][1][S][S]: log1p of 2x2-binned intensities / 10 (see
- *           dmnet_preprocess)
+ *   input   [n][1][S][S]: log1p of 2x2-binned intensities / 10, zero
+ *           frequency at the centre (see dmnet_preprocess)
  *   encoder level l = 0..L-1, C_l = C0 * 2^l channels: two 3x3 convolutions
  *           (zero padding) each followed by ReLU; 2x2 average pooling between
  *           levels
@@ -93,7 +93,10 @@ dm_status dmnet_train_step(dmnet* net, const float* x_dev, const float* target_d
                            int32_t n, float* loss_host);
 
 /* x [n][1][F/2][F/2] = log1p(2x2 sums of I [n][F][F]) / 10 (negative
- * intensities count as 0).  F/2 must equal the network size S. */
+ * intensities count as 0), the binned frame shifted by S/2 in both
+ * directions so that the block holding the zero frequency (frame pixel
+ * [0][0], the DFT convention of dm.h) lands at [S/2][S/2].  F/2 must equal
+ * the network size S. */
 dm_status dmnet_preprocess(dmnet* net, const float* I_dev, int32_t n, int32_t frame,
                            float* x_dev);
 

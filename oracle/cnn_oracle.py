@@ -236,10 +236,14 @@ def loss_and_grads(params, x, target, levels: int = 4, act_round=None):
 # input and output maps between frames and the network
 # ---------------------------------------------------------------------------
 def preprocess(I):
-    """x[n][0] = log1p(2x2 block sums of max(I, 0)) / 10; I: [N][F][F]."""
+    """x[n][0] = log1p(2x2 block sums of max(I, 0)) / 10, with the block
+    image rolled by S/2 = F/4 along both axes so that the block holding the
+    zero frequency (pixel [0][0] of the unshifted DFT) sits at [S/2][S/2];
+    I: [N][F][F]."""
     I = np.maximum(np.asarray(I, dtype=np.float64), 0.0)
     n, f, _ = I.shape
     s = I.reshape(n, f // 2, 2, f // 2, 2).sum(axis=(2, 4))
+    s = np.roll(s, (f // 4, f // 4), axis=(1, 2))
     return (np.log1p(s) / 10.0)[:, None]
 
 

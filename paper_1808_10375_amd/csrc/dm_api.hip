@@ -97,9 +97,18 @@ int cols_per_block(int F, int M) {
   return p;
 }
 
+// rows per block of the power-of-two row kernels, taken from their own
+// RowCfg so that the eps_psi partials they write always fit the buffer sized
+// from it
 int row_block(int F) {
-  const int B = F / 16;
-  return std::min(256 / B, F);
+  switch (F) {
+    case 16: return dmk::RowCfg<16>::RB;
+    case 32: return dmk::RowCfg<32>::RB;
+    case 64: return dmk::RowCfg<64>::RB;
+    case 128: return dmk::RowCfg<128>::RB;
+    case 256: return dmk::RowCfg<256>::RB;
+  }
+  return F;
 }
 
 // row blocks per frame of the three-kernel path (one eps_psi partial each)

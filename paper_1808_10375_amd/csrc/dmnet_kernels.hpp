@@ -751,7 +751,8 @@ __global__ void k_preprocess(const float* __restrict__ I, int F, int n, float* _
        e += (long)gridDim.x * blockDim.x) {
     const int nn = (int)(e / (S * S));
     const int q = (int)(e % (S * S));
-    const int i = q / S, j = q % S;
+    // zero frequency (pixel 0, 0 of the frame) to the centre of the input
+    const int i = (q / S + S / 2) % S, j = (q % S + S / 2) % S;
     const float* b = I + (long)nn * F * F + (2 * i) * F + 2 * j;
     const float s = fmaxf(b[0], 0.f) + fmaxf(b[1], 0.f) + fmaxf(b[F], 0.f) + fmaxf(b[F + 1], 0.f);
     x[e] = log1pf(s) * 0.1f;

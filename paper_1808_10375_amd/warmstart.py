@@ -80,10 +80,34 @@ def patch_targets(O: np.ndarray, pos: np.ndarray, f: int = FRAME) -> np.ndarray:
     return out
 
 
+def lit_mask(P0: np.ndarray, level: float = 0.01) -> np.ndarray:
+    """[f/2][f/2] weights in [0, 1] of the window's pixels in what one frame
+    determines: sum_k |P0_k|^2 (2x2 averages) over `level` of its peak,
+    clipped at 1.  Outside the probe's footprint a frame carries nothing
+    about the object, and the Eq. 5 stitch weights it by |P0|^2 anyway."""
+    d = np.sum(np.abs(P0.astype(np.complex128)) ** 2, axis=0)
+    f = d.shape[0]
+    d = d.reshape(f // 2, 2, f // 2, 2).mean(axis=(1, 3))
+    return np.minimum(1.0, d / (level * d.max()))
+
+
+def masked_targets(O: np.ndarray, pos: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Patch targets 1 + mask * (patch - 1): the object where the probe lights
+    the window, the flat value 1 where it does not."""
+    t = patch_targets(O, pos)
+    t[:, 0] = 1.0 + mask * (t[:, 0] - 1.0)
+    t[:, 1] = mask * t[:, 1]
+    return t
+
+
 def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
-               group: int = 16, net=None, device="cuda:0"):
-    """(x [P][1][64][64], target [P][2][64][64]) on the device, from DM runs of
-    `n_iter` iterations on the scans of `seeds`, `group` scans per batch."""
+               group: int = 16, net=None, device="cuda:0", targets: str = "truth"):
+    """(x [P][1][64][64], target [P][2][64][64]) on the device for the scans of
+    `seeds`.  targets="truth": the synthetic scan's own object, in the gauge of
+    the flat start (normalise_object) and masked to the probe's footprint
+    (masked_targets).  targets="dm": the object that `n_iter` DM iterations
+    reconstruct from the cold start (same normalisation, unmasked), `group`
+    scans per batch."""
     import torch
     from .dm import DMBatch
     xs, ts = [], []
@@ -91,19 +115,25 @@ def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
         t0 = time.time()
         scans = [training_scan(s, n_frames, obj) for s in seeds[g0:g0 + group]]
         t1 = time.time()
-        batch = DMBatch([dict(I=s.I, pos=s.pos, P0=s.P0, O0=s.O0) for s in scans],
-                        device=device)
-        batch.iterate(n_iter)
+        if targets == "dm":
+            batch = DMBatch([dict(I=s.I, pos=s.pos, P0=s.P0, O0=s.O0) for s in scans],
+                            device=device)
+            batch.iterate(n_iter)
         for k, s in enumerate(scans):
-            O = batch.object(k).cpu().numpy().astype(np.complex128)
-            w = illumination(s.P0, s.pos, O.shape)
-            t = patch_targets(normalise_object(O, w), s.pos)
+            w = illumination(s.P0, s.pos, s.O0.shape)
+            if targets == "dm":
+                O = batch.object(k).cpu().numpy().astype(np.complex128)
+                t = patch_targets(normalise_object(O, w), s.pos)
+            else:
+                O = s.O_true.astype(np.complex128)
+                t = masked_targets(normalise_object(O, w), s.pos, lit_mask(s.P0))
             I = torch.as_tensor(s.I).to(device)
             xs.append(net.preprocess(I))
             ts.append(torch.as_tensor(t).to(device))
-        batch.free()
+        if targets == "dm":
+            batch.free()
         log(f"pairs: scans {g0}..{g0 + len(scans) - 1}: generate {t1 - t0:.1f} s, "
-            f"DM {n_iter} it + targets {time.time() - t1:.1f} s")
+            f"targets {time.time() - t1:.1f} s")
     return torch.cat(xs), torch.cat(ts)
 
 
@@ -221,7 +251,7 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
             errs = [[e["eps_probe"] for e in b.error_history(k)] for k in range(len(scans))]
             b.free()
         res[form] = {"err": errs, "obj_err": obj_err, "init_s": t_init}
-    levels = (1e-3, 1e-2, 3e-2, 1e-1)
+    levels = (1e-3, 1e-2, 2e-2, 3e-2, 1e-1)
     out = {"n_iter": n_iter, "scans": len(scans), "per_scan": []}
     for k in range(len(scans)):
         ec, ew = res["cold"]["err"][k], res["warm"]["err"][k]
@@ -232,6 +262,12 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
                        for f, e in (("cold", ec), ("warm", ew))},
             "iters_to": {f"{lv:g}": {"cold": first_at_or_below(ec, lv),
                                      "warm": first_at_or_below(ew, lv)} for lv in levels},
+            # err <= 1e-3 is out of reach of Poisson data: the level is 1.1x the
+            # cold start's err after n_iter iterations (the cold run stands in for
+            # the converged reference on these scans)
+            "iters_to_1.1x_final": {"level": 1.1 * ec[-1],
+                                    "cold": first_at_or_below(ec, 1.1 * ec[-1]),
+                                    "warm": first_at_or_below(ew, 1.1 * ec[-1])},
             "object_error": {f: {str(c): res[f]["obj_err"][c][k] for c in res[f]["obj_err"]}
                              for f in ("cold", "warm")},
         }
@@ -243,6 +279,12 @@ def compare(net, scans, n_iter: int, batch: int, device="cuda:0", checkpoints=(1
         reached = [x for x in v if x is not None]
         return {"median": float(np.median(reached)) if reached else None,
                 "reached": len(reached)}
+    fin = {f: [r["iters_to_1.1x_final"][f] for r in out["per_scan"]] for f in ("cold", "warm")}
+    out["iters_to_1.1x_final"] = {
+        "median": {f: float(np.median([v if v is not None else n_iter + 1 for v in fin[f]]))
+                   for f in fin},
+        "saved_per_scan": [(c - w) if (c is not None and w is not None) else None
+                           for c, w in zip(fin["cold"], fin["warm"])]}
     out["median"] = {
         "iters_to": {f"{lv:g}": {f: med_iters(lv, f) for f in ("cold", "warm")}
                      for lv in levels},
@@ -285,6 +327,7 @@ def main(argv=None):
     ap.add_argument("--train-frames", type=int, default=256)
     ap.add_argument("--train-obj", type=int, default=384)
     ap.add_argument("--dm-iters", type=int, default=100)
+    ap.add_argument("--targets", choices=["truth", "dm"], default="truth")
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -312,9 +355,10 @@ def main(argv=None):
         t0 = time.time()
         seeds = list(range(10000, 10000 + a.train_scans))
         vseeds = list(range(20000, 20000 + a.val_scans))
-        x, t = make_pairs(seeds, a.dm_iters, a.train_frames, a.train_obj, net=net, device=dev)
+        x, t = make_pairs(seeds, a.dm_iters, a.train_frames, a.train_obj, net=net, device=dev,
+                          targets=a.targets)
         xv, tv = make_pairs(vseeds, a.dm_iters, a.train_frames, a.train_obj, net=net,
-                            device=dev)
+                            device=dev, targets=a.targets)
         t_pairs = time.time() - t0
         log(f"pairs: {x.shape[0]} training, {xv.shape[0]} validation ({t_pairs:.0f} s)")
         v0 = validation_loss(net, xv, tv, a.batch)
@@ -322,7 +366,8 @@ def main(argv=None):
                                      max_seconds=a.max_train_s)
         report["training"] = {
             "scans": a.train_scans, "frames_per_scan": a.train_frames,
-            "object": a.train_obj, "dm_iters": a.dm_iters, "pairs": int(x.shape[0]),
+            "object": a.train_obj, "targets": a.targets,
+            "dm_iters": a.dm_iters if a.targets == "dm" else None, "pairs": int(x.shape[0]),
             "validation_pairs": int(xv.shape[0]), "epochs": a.epochs, "batch": a.batch,
             "lr": a.lr, "steps": steps, "pairs_s": t_pairs, "train_s": t_train,
             "samples_per_s": steps * a.batch / t_train, "val_loss_initial": v0,
@@ -345,6 +390,7 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write(line + "\n")
     print(json.dumps({"median": report["evaluation"]["median"],
+                      "iters_to_1.1x_final": report["evaluation"]["iters_to_1.1x_final"],
                       "median_object_error": report["evaluation"]["median_object_error"]}))
 
 

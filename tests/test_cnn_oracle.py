@@ -88,9 +88,18 @@ def test_preprocess_constant_frames_and_clipping():
     assert np.allclose(x[0], np.log(13.0) / 10.0, atol=1e-15)
     assert np.all(x[1] == 0.0)
     J = np.zeros((1, 4, 4))
-    J[0, 2, 3] = np.e - 1.0                     # one count in block (1, 1)
-    x = net.preprocess(J)[0, 0]
-    assert abs(x[1, 1] - 0.1) < 1e-15 and np.count_nonzero(x) == 1
+    J[0, 2, 3] = np.e - 1.0                     # one count in block (1, 1),
+    x = net.preprocess(J)[0, 0]                 # which moves to (0, 0)
+    assert abs(x[0, 0] - 0.1) < 1e-15 and np.count_nonzero(x) == 1
+    # the zero-frequency pixel of a 16 x 16 frame lands at the centre block
+    # (4, 4) of the 8 x 8 input, its negative-frequency neighbours (pixel 15)
+    # in the block before it
+    K = np.zeros((1, 16, 16))
+    K[0, 0, 0] = np.e - 1.0
+    K[0, 15, 15] = np.e ** 2 - 1.0
+    x = net.preprocess(K)[0, 0]
+    assert abs(x[4, 4] - 0.1) < 1e-15 and abs(x[3, 3] - 0.2) < 1e-15
+    assert np.count_nonzero(x) == 2
 
 
 def test_patches_reproduce_constants_and_interior_linear_ramps():

@@ -643,7 +643,7 @@ template <int F>
 dm_status launch_views_multipass(dm_ctx* c) {
   constexpr int B = F / 16, RB = dmk::RowCfg<F>::RB, NT = dmk::RowCfg<F>::NT;
   const int M = c->M, MT = c->M * c->L;  // probe modes, frames per view
-  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views * MT, F / RB), dim3(NT), 0,
+  hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views, F / RB), dim3(NT), 0,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_rows_fwd");
   // the column kernel sums the modulus over all MT frames of a view

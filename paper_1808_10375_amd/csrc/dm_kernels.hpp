@@ -677,7 +677,11 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
             const int l = (g + B * i) + 16 * l2;
             const float iv = fmaxf(bI[c * (F + 1) + l], 0.f);
             const float sv = S[v][r];
-            const float g = (sv > FLT_MIN) ? sqrtf(iv / sv) * inv_ff : 0.f;
+            // hardware reciprocal and square root (1 ulp each) instead of the
+            // correctly rounded division and root: branch-free, and the
+            // scale is within 3 ulp of sqrt(I / S) / F^2
+            const float q = iv * __builtin_amdgcn_rcpf(fmaxf(sv, FLT_MIN));
+            const float g = (sv > FLT_MIN) ? __builtin_amdgcn_sqrtf(q) * inv_ff : 0.f;
             S[v][r] = kDirect ? beta * g - inv_ff : g;
           }
       }

@@ -191,6 +191,13 @@ __device__ __forceinline__ void bstore2_nt(rsrc_t r, float2 x, int voff, int sof
 // loop.
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Index arrays that no kernel writes (view positions, the view order, the
+// tile lists) are read through constant-address-space pointers: where the
+// index is uniform in a wave the load goes through the scalar cache instead
+// of the vector memory path.
+typedef const __attribute__((address_space(4))) int* kidx_t;
+__device__ __forceinline__ kidx_t kidx(const int* p) { return (kidx_t)p; }
+
 // Index that is the same for every lane of a wave when F >= 64 (a wave's 64
 // lanes then share t / F); keeping it in an SGPR makes its table loads scalar.
 template <int F>

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_fused(
   const float* __restrict__ I = sc.I;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
-  const int* __restrict__ pos = sc.pos;
+  const kidx_t pos = kidx(sc.pos);
   float2* __restrict__ opart = sc.opart;
   float* __restrict__ gscr = sc.gscr;
   float* __restrict__ err_psi = sc.err_psi;
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
     const int j = uni(vm.y);
     const int H = uni(sc.H), W = uni(sc.W);
     const float beta = sc.beta;
-    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
+    const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
     const rsrc_t rpsi = make_rsrc(sc.psi + (size_t)j * M * FF, (uint32_t)(M * FF * 8));
     const rsrc_t rP = make_rsrc(sc.P, (uint32_t)(M * FF * 8));
     const rsrc_t rO = make_rsrc(sc.O, (uint32_t)((size_t)H * W * 8));
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
   const float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
-  const int* __restrict__ pos = sc.pos;
+  const kidx_t pos = kidx(sc.pos);
   float2* __restrict__ T = sc.tspec;
   const int W = uni(sc.W);
   const int rl = t / B, n2 = t % B;
@@ -1044,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(
   float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ P = sc.P;
   const float2* __restrict__ O = sc.O;
-  const int* __restrict__ pos = sc.pos;
+  const kidx_t pos = kidx(sc.pos);
   const float2* __restrict__ T = sc.tspec;
   float2* __restrict__ opart = sc.opart;
   float* __restrict__ err_psi = sc.err_psi;
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   __shared__ float red[2 * ((256 * G + 63) / 64)];
   __shared__ float2 pnum[G > 1 ? (G - 1) : 1][T * T];
   __shared__ double pden[G > 1 ? (G - 1) : 1][T * T];
-  const int q = threadIdx.x >> 8;   // group
+  const int q = uni(threadIdx.x >> 8);  // group (uniform in a wave)
   const int t = threadIdx.x & 255;  // pixel lane within the group
   const int2 tm = tmap[xcd_group_slot(blockIdx.x, gridDim.x)];
   const ScanDev& sc = scans[tm.x];
@@ -1171,9 +1171,10 @@ __global__ __launch_bounds__(256 * G) void k_object(const ScanDev* __restrict__ 
   const float2* __restrict__ opart = sc.opart;
   const float* __restrict__ D = sc.D;
   float2* __restrict__ O = sc.O + (size_t)l * uni(sc.H) * uni(sc.W);
-  const int* __restrict__ pos = sc.pos;
-  const int* __restrict__ tile_ptr = sc.tile_ptr;
-  const int* __restrict__ tile_views = sc.tile_views;
+  // every index here is uniform in a wave: scalar loads
+  const kidx_t pos = kidx(sc.pos);
+  const kidx_t tile_ptr = kidx(sc.tile_ptr);
+  const kidx_t tile_views = kidx(sc.tile_views);
   float* __restrict__ err_obj = sc.err_obj;
   const int H = uni(sc.H), W = uni(sc.W), tiles_x = uni(sc.tiles_x);
   const int ty = tile / tiles_x, tx = tile % tiles_x;
@@ -1287,8 +1288,8 @@ __global__ __launch_bounds__(256) void k_probe_partial(const ScanDev* __restrict
   const int cidx = cm.y;
   const float2* __restrict__ psi = sc.psi;
   const float2* __restrict__ O = sc.O;
-  const int* __restrict__ pos = sc.pos;
-  const int* __restrict__ order = sc.order;
+  const kidx_t pos = kidx(sc.pos);
+  const kidx_t order = kidx(sc.order);
   float2* __restrict__ num_part = sc.num_part;
   float* __restrict__ den_part = sc.den_part;
   const int N = sc.N, W = sc.W, chunk = sc.chunk;

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kMfRowsThreads) void k_mf_rows_fwd(const ScanDev* _
     const ScanDev& sc = scans[vm.x];
     const int j = uni(vm.y);
     const int W = uni(sc.W);
-    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
+    const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
     const float2* __restrict__ psi = sc.psi + ((size_t)j * M + m) * FF;
     const float2* __restrict__ P = sc.P + (size_t)m * FF;
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kMfRowsThreads) void k_mf_rows_inv(const ScanDev* _
     const int j = uni(vm.y);
     const int W = uni(sc.W);
     const float beta = sc.beta;
-    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
+    const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
     const float2* __restrict__ O = sc.O + (size_t)y0 * W + x0;
     const int rbase = 16 * wave;
     float2 oacc[kMfNt][4];

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
   float2 a[R] = {};
   if (active && tl < Q) {
     const int W = uni(sc.W);
-    const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
+    const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
     const float2* __restrict__ pm = sc.psi + (size_t)jm * FF + (size_t)row * F;
     const float2* __restrict__ Pm = sc.P + (size_t)m * FF + (size_t)row * F;
     const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
   const bool owner = active && tl < Q;  // holds pixels Q n1 + tl of the row
   const int W = uni(sc.W);
   const float beta = sc.beta;
-  const int y0 = uni(sc.pos[2 * j]), x0 = uni(sc.pos[2 * j + 1]);
+  const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
   const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
   mix_load_tables<F>(tw, twl, twq, t, NT);
   float2 oacc[R];

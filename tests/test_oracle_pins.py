@@ -217,6 +217,30 @@ def test_probe_update_is_weighted_least_squares():
     assert rel(P_new, sol.reshape(m, f, f)) < 1e-12
 
 
+def test_updates_at_one_pixel_need_only_what_reaches_it():
+    """The sampled checks of the full-size tests rest on two locality facts of
+    Eqs. 4-5: O' at a pixel depends only on the views whose window covers it,
+    and P'_k at a probe pixel (u, v) is the probe update of 1 x 1 frames cut
+    at (u, v) with every window corner moved by (u, v)."""
+    rng = np.random.default_rng(9)
+    n, m, f, h, w = 9, 3, 6, 14, 13
+    P = crand(rng, m, f, f)
+    psi = crand(rng, n, m, f, f)
+    O_old = crand(rng, h, w)
+    pos = np.stack([rng.integers(0, h - f + 1, n), rng.integers(0, w - f + 1, n)], axis=1)
+    O_all, _ = dm.object_update(psi, P, O_old, pos)
+    for (y, x) in [(5, 6), (0, 0), (h - 1, w - 1), (7, 2)]:
+        jj = np.nonzero((pos[:, 0] <= y) & (y < pos[:, 0] + f) &
+                        (pos[:, 1] <= x) & (x < pos[:, 1] + f))[0]
+        O_sub, _ = dm.object_update(psi[jj], P, O_old, pos[jj])
+        assert abs(O_sub[y, x] - O_all[y, x]) <= 1e-14 * max(abs(O_all[y, x]), 1.0)
+    P_all, _ = dm.probe_update(psi, O_old, P, pos)
+    for (u, v) in [(0, 0), (2, 5), (5, 5), (3, 1)]:
+        P_uv, _ = dm.probe_update(psi[:, :, u:u + 1, v:v + 1], O_old, P[:, u:u + 1, v:v + 1],
+                                  pos + np.array([u, v]))
+        assert rel(P_uv[:, 0, 0], P_all[:, u, v]) < 1e-14
+
+
 # ---------------------------------------------------------------------------
 # the whole iteration
 # ---------------------------------------------------------------------------

@@ -8,11 +8,12 @@ The whole FP64 iteration is too slow for a test, so the oracle is applied
 where it can be computed one piece at a time:
   * psi' of sampled views: the view update (Eq. 3 with F_c) of view j
     depends only on psi_j, P, O[window_j] and I_j;
-  * O' at sampled object pixels: Eq. 5 in FP64 over every view that covers
-    the pixel, from the GPU's psi' (gathered on the device) and the old
-    probe;
-  * P' at sampled probe pixels: Eq. 4 in FP64 over all 10000 views, from the
-    GPU's psi' and the GPU's new object.
+  * O' at sampled object pixels: the oracle's object update (Eq. 5) over
+    every view that covers the pixel (the other views add nothing there),
+    from the GPU's psi' of those views and the old probe;
+  * P' at sampled probe pixels: the oracle's probe update (Eq. 4) over all
+    10000 views on 1 x 1 frames cut at the pixel (each window corner moved
+    by the pixel's offset), from the GPU's psi' and the GPU's new object.
 Bar: 1e-5 relative (L2 over the sampled views; per sampled pixel)."""
 import sys
 
@@ -79,37 +80,30 @@ def test_flyscan_10000_views_full_size_sampled(frame):
     say(f"  psi' of {len(js)} sampled views: rel L2 {r_psi:.2e}")
     assert r_psi <= TOL
 
-    # O' at sampled object pixels (Eq. 5 from the GPU's psi' and P0)
+    # O' at sampled object pixels: the oracle's Eq. 5 over the covering views
     O_g = O_t.cpu().numpy()
     worst = 0.0
     for (y, x) in cfg["obj_px"]:
         jj = np.nonzero((pos[:, 0] <= y) & (y < pos[:, 0] + f) &
                         (pos[:, 1] <= x) & (x < pos[:, 1] + f))[0]
-        u, v = y - pos[jj, 0], x - pos[jj, 1]
-        it_j = torch.as_tensor(jj, device=dev)[:, None]
-        it_k = torch.arange(m, device=dev)[None, :]
-        vals = psi_t[it_j, it_k, torch.as_tensor(u, device=dev)[:, None],
-                     torch.as_tensor(v, device=dev)[:, None]].cpu().numpy().astype(np.complex128)
-        pk = P0[:, u, v].T                                   # [views][modes]
-        num = np.sum(np.conj(pk) * vals)
-        den = np.sum(np.abs(pk) ** 2)
-        ref = num / den
+        psi_jj = psi_t[torch.as_tensor(jj, device=dev)].cpu().numpy()
+        O_ref, _ = oracle.object_update(psi_jj, P0, O0, pos[jj])
+        del psi_jj
+        ref = O_ref[y, x]
         e = abs(O_g[y, x] - ref) / abs(ref)
         worst = max(worst, e)
         say(f"  O'[{y},{x}]: {len(jj)} views, rel {e:.2e}")
     assert worst <= TOL
 
-    # P' at sampled probe pixels (Eq. 4 over all views, GPU psi' and new O)
+    # P' at sampled probe pixels: the oracle's Eq. 4 over all views, on the
+    # 1 x 1 frames at (u, v) with the window corners moved by (u, v)
     P_g = P_t.cpu().numpy()
     worst = 0.0
     for (u, v) in cfg["probe_px"]:
-        o = O_t[torch.as_tensor(pos[:, 0] + u, device=dev),
-                torch.as_tensor(pos[:, 1] + v, device=dev)].cpu().numpy().astype(np.complex128)
-        vals = psi_t[:, :, u, v].cpu().numpy().astype(np.complex128)   # [views][modes]
-        num = np.sum(np.conj(o)[:, None] * vals, axis=0)
-        den = np.sum(np.abs(o) ** 2)
-        ref = num / den
-        e = rel(P_g[:, u, v], ref)
+        psi_uv = psi_t[:, :, u:u + 1, v:v + 1].cpu().numpy()
+        P_ref, _ = oracle.probe_update(psi_uv, O_g, P0[:, u:u + 1, v:v + 1],
+                                       pos + np.array([u, v]))
+        e = rel(P_g[:, u, v], P_ref[:, 0, 0])
         worst = max(worst, e)
         say(f"  P'[:, {u}, {v}]: rel {e:.2e}")
     assert worst <= TOL

@@ -821,14 +821,14 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
 // their RB x F tiles through LDS and touch T along rows (RB consecutive
 // values of one line per run).
 // ---------------------------------------------------------------------------
-// Loads and stores with the non-temporal hint: the power-of-two
-// three-kernel path streams psi and the spectrum buffer through them, and
-// the probe sums read psi' so, so that the probe, the object and the
-// intensities stay in the caches (at 10000 x 8 x 256^2 the view update
-// takes 62.3 ms so, 65.4 ms with every access cached; the probe sums 6.05
+// Loads and stores with the non-temporal hint.  The power-of-two
+// three-kernel path streams psi and the spectrum buffer through them and
+// the probe sums read psi' through them, so that the probe, the object and
+// the intensities stay in the caches (at 10000 x 8 x 256^2 the view update
+// takes 62.3 ms with the hints and 65.4 ms without; the probe sums 6.05
 // against 6.78 ms).  The mixed-radix kernels read the buffer along columns,
-// where neighbouring lanes share cache lines that the hint would give up
-// (their view update took 52 ms so, against 28 ms).
+// where neighbouring lanes share cache lines that the hint would give up:
+// their view update took 52 ms with it, against 28 ms.
 typedef float ntf2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 ntl2(const float2* p) {
   const ntf2 v = __builtin_nontemporal_load(reinterpret_cast<const ntf2*>(p));

@@ -405,7 +405,7 @@ def bench_probe_first(scan, steps: int, warmup: int):
 
 
 def run_scan(scan, steps: int, warmup: int, conv_iters: int, flags: int = 0,
-             precision: int = 0, view_path=None):
+             precision: int = 0, view_path=None, autotune: bool = False):
     """Warm-up, then `steps` timed iterations of one scan (inputs already in
     HBM, torch.cuda.synchronize() on both sides), the phase times of the
     timed iterations, and the err curve of conv_iters iterations from the
@@ -421,10 +421,13 @@ def run_scan(scan, steps: int, warmup: int, conv_iters: int, flags: int = 0,
         ctx = dm.DMContext(I, scan.pos, P0, O0, beta=scan.beta,
                            flags=flags | dm.DM_FLAG_PHASE_TIMING, stream=stream,
                            precision=precision)
+        if autotune:
+            ctx.autotune(reps=3)  # restores the cold state afterwards
         if view_path is not None:
             tune = ctx.tuning()
             ctx.set_tuning(tune["obj_tile"], tune["probe_chunks"], view_path)
         vp = ctx.tuning()["view_path"]
+        tuning = ctx.tuning()
         ctx.iterate(warmup)
         ctx.phase_times()  # drop the warm-up marks (synchronises)
         torch.cuda.synchronize()
@@ -441,7 +444,7 @@ def run_scan(scan, steps: int, warmup: int, conv_iters: int, flags: int = 0,
         ctx.free()
         del I, P0, O0
     return {"elapsed": elapsed, "phases": phases, "n_timed": n_timed, "hist": hist,
-            "view_path": vp}
+            "view_path": vp, "tuning": tuning}
 
 
 def view_roofline(n, m, f, r, psi_error_last=False, traffic=None):
@@ -507,6 +510,9 @@ def main():
                          "(DM_FLAG_PSI_ERROR_LAST; not a headline configuration)")
     ap.add_argument("--view-path", type=int, default=None, choices=[0, 1, 2, 3, 4, 5],
                     help="override the library's default view kernel (dm_tuning.view_path)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate launch shapes first (dm_autotune) and run the "
+                         "fastest instead of the library's defaults")
     ap.add_argument("--multipass", action="store_true",
                     help="use the three-kernel transform path instead of the fused one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -570,7 +576,8 @@ def main():
     flags = ((dm.DM_FLAG_MULTIPASS if args.multipass else 0)
              | (dm.DM_FLAG_PSI_ERROR_LAST if args.psi_error_last else 0))
     prec = dm.DM_BF16X3_DFT if args.precision == "bf16x3" else dm.DM_FP32_FFT
-    r = run_scan(scan, args.steps, args.warmup, args.conv_iters, flags, prec, args.view_path)
+    r = run_scan(scan, args.steps, args.warmup, args.conv_iters, flags, prec, args.view_path,
+                 args.autotune)
     elapsed, phases, n_timed, hist = r["elapsed"], r["phases"], r["n_timed"], r["hist"]
     view_path = r["view_path"]
 
@@ -602,6 +609,7 @@ def main():
         "step_roofline_frac": step_alg_bytes(n, m, f) / (ms_per_step * 1e-3) / 1e9
         / HBM_PEAK_GBS,
         "phase_ms_per_iter": {k: v / max(n_timed, 1) for k, v in phases.items()},
+        "tuning": dict(r["tuning"], autotuned=bool(args.autotune)),
         "iters_to_err_1e-3": reach,
         "err_at": {str(i): errs[i - 1] for i in (1, 10, 20, 50, 100) if i <= len(errs)},
     }

@@ -43,8 +43,12 @@ bool is_mixed(int F) { return F == 188 || F == 200; }
 // ---------------------------------------------------------------------------
 int n_pblk(int F) { return (F * F + 255) / 256; }
 
+// view chunks of the probe partial sums: about 1024 blocks of 256 pixels,
+// four per compute unit (dm_autotune chose half the earlier 2048 at 2500 x
+// 5 x 128^2, 10000 x 8 x 256^2 and 10000 x 4 x 188^2: 0.27 against 0.29 ms
+// for the sums and the final division at 128^2, equal at the other two)
 int default_chunks(int F) {
-  int C = (2048 + n_pblk(F) - 1) / n_pblk(F);
+  int C = (1024 + n_pblk(F) - 1) / n_pblk(F);
   return std::max(1, std::min(C, DM_MAX_PROBE_CHUNKS));
 }
 

@@ -630,24 +630,29 @@ __global__ __launch_bounds__(F * F / (16 * V)) void k_fourier_stream(
     for (int v = 0; v < V; ++v)
 #pragma unroll
       for (int r = 0; r < 16; ++r) S[v][r] = 0.f;
-    // ---- pass 1 (loads in batches, all of a batch issued before its use)
+    // ---- pass 1: all of the mode's psi first, into the transform registers
+    // (one memory latency per mode instead of two: 1.95 -> 1.88 ms at 2500 x
+    // 5 x 128^2), then the cached probe and object in two batches
     for (int m = 0; m < M; ++m) {
       const int sm = m * FF * 8;
 #pragma unroll
       for (int v = 0; v < V; ++v)
 #pragma unroll
+        for (int r = 0; r < 16; ++r) a[v][r] = ld_psi1(sm + rowF(v, r));
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
         for (int b = 0; b < 16; b += 8) {
-          float2 ps[8], pp[8], oo[8];
+          float2 pp[8], oo[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            ps[k] = ld_psi1(sm + rowF(v, b + k));
             pp[k] = bload2(rP, vF, sm + rowF(v, b + k));
             oo[k] = bload2(rO, vO, sO + rowO(v, b + k));
           }
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const float2 phi = cmul(pp[k], oo[k]);
-            a[v][b + k] = make_float2(2.f * phi.x - ps[k].x, 2.f * phi.y - ps[k].y);
+            a[v][b + k] = make_float2(2.f * phi.x - a[v][b + k].x, 2.f * phi.y - a[v][b + k].y);
           }
         }
       Frame2D<F, -1, V>::fwd(a, buf, tw, c, g0);

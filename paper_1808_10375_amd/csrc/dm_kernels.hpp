@@ -974,6 +974,17 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
   const int m = t / (B * CB);
   const int line = m * CB + c;
   float2* __restrict__ Tm = T + ((size_t)j * M + m) * FF + (size_t)(col0 + c) * F;
+  // the first KI of this thread's intensities (of the pixels whose scale it
+  // forms below) go out before the transform, which hides their latency
+  constexpr int KI = 4;
+  const float* __restrict__ Ij = I + (size_t)j * FF + col0;
+  float ivp[KI];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int p = t + i * (int)blockDim.x;
+    const int cc = p / F, kk = p - cc * F;
+    ivp[i] = (p < CB * F) ? Ij[(size_t)kk * F + cc] : 0.f;
+  }
   float2 a[16];
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) a[n1] = ntl2(&Tm[B * n1 + n2]);
@@ -1007,9 +1018,19 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) s[line * LS + (n2 + B * i) + 16 * k2] = cabs2(a[i * B + k2]);
   __syncthreads();
-  const float* __restrict__ Ij = I + (size_t)j * FF + col0;
   const float inv_ff = 1.0f / (float)FF;
-  for (int p = t; p < CB * F; p += blockDim.x) {
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int p = t + i * (int)blockDim.x;
+    if (p < CB * F) {
+      const int cc = p / F, kk = p - cc * F;
+      float sum = 0.f;
+      for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + cc) * LS + kk];
+      const float iv = fmaxf(ivp[i], 0.f);
+      gsh[cc * LS + kk] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    }
+  }
+  for (int p = t + KI * (int)blockDim.x; p < CB * F; p += blockDim.x) {
     const int cc = p / F, kk = p - cc * F;
     float sum = 0.f;
     for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + cc) * LS + kk];

@@ -10,8 +10,9 @@ stays the fallback and the reference the warm start is measured against.
 
 Every arithmetic step of the reconstruction and of the network runs in
 libdm's kernels (dm.py, dmnet.py).  Host code here only prepares training
-targets from reconstructed objects (global phase and scale normalisation,
-window extraction, 2x2 binning) and bookkeeps.
+targets from reconstructed objects (phase ramp, global phase and scale
+normalisation, window extraction, 2x2 binning, the probe-footprint mask) and
+bookkeeps.
 
     python -m paper_1808_10375_amd.warmstart --out report.json
 """
@@ -70,6 +71,18 @@ def normalise_object(O: np.ndarray, weight: np.ndarray, floor: float = 0.01) -> 
     return out
 
 
+def remove_phase_ramp(O: np.ndarray, weight: np.ndarray) -> np.ndarray:
+    """Remove the linear phase ramp that the data leave free (P e^{iq.r} with
+    O e^{-iq.r} models the same intensities): q is the mean phase step
+    between neighbouring well-lit pixels along each axis, which a zero-mean
+    random phase field does not bias."""
+    lit = weight >= 0.1 * weight.max()
+    gx = np.sum((O[:, 1:] * np.conj(O[:, :-1]))[lit[:, 1:] & lit[:, :-1]])
+    gy = np.sum((O[1:, :] * np.conj(O[:-1, :]))[lit[1:, :] & lit[:-1, :]])
+    y, x = np.mgrid[0:O.shape[0], 0:O.shape[1]]
+    return O * np.exp(-1j * (np.angle(gx) * x + np.angle(gy) * y))
+
+
 def patch_targets(O: np.ndarray, pos: np.ndarray, f: int = FRAME) -> np.ndarray:
     """[N][2][f/2][f/2] float32: 2x2 averages of the object under each window."""
     out = np.empty((len(pos), 2, f // 2, f // 2), dtype=np.float32)
@@ -101,13 +114,15 @@ def masked_targets(O: np.ndarray, pos: np.ndarray, mask: np.ndarray) -> np.ndarr
 
 
 def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
-               group: int = 16, net=None, device="cuda:0", targets: str = "truth"):
+               group: int = 16, net=None, device="cuda:0", targets: str = "dm-masked"):
     """(x [P][1][64][64], target [P][2][64][64]) on the device for the scans of
-    `seeds`.  targets="truth": the synthetic scan's own object, in the gauge of
-    the flat start (normalise_object) and masked to the probe's footprint
-    (masked_targets).  targets="dm": the object that `n_iter` DM iterations
-    reconstruct from the cold start (same normalisation, unmasked), `group`
-    scans per batch."""
+    `seeds`.  targets="dm-masked" (the default): the object that `n_iter` DM
+    iterations reconstruct from the cold start (`group` scans per batch),
+    its free phase ramp removed (remove_phase_ramp), in the gauge of the flat
+    start (normalise_object) and masked to the probe's footprint
+    (masked_targets).  targets="dm": the same reconstruction, normalised but
+    neither de-ramped nor masked.  targets="truth": the synthetic scan's own
+    object, normalised and masked."""
     import torch
     from .dm import DMBatch
     xs, ts = [], []
@@ -115,7 +130,7 @@ def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
         t0 = time.time()
         scans = [training_scan(s, n_frames, obj) for s in seeds[g0:g0 + group]]
         t1 = time.time()
-        if targets == "dm":
+        if targets.startswith("dm"):
             batch = DMBatch([dict(I=s.I, pos=s.pos, P0=s.P0, O0=s.O0) for s in scans],
                             device=device)
             batch.iterate(n_iter)
@@ -124,13 +139,17 @@ def make_pairs(seeds, n_iter: int = 100, n_frames: int = 256, obj: int = 384,
             if targets == "dm":
                 O = batch.object(k).cpu().numpy().astype(np.complex128)
                 t = patch_targets(normalise_object(O, w), s.pos)
+            elif targets == "dm-masked":
+                O = batch.object(k).cpu().numpy().astype(np.complex128)
+                O = normalise_object(remove_phase_ramp(O, w), w)
+                t = masked_targets(O, s.pos, lit_mask(s.P0))
             else:
                 O = s.O_true.astype(np.complex128)
                 t = masked_targets(normalise_object(O, w), s.pos, lit_mask(s.P0))
             I = torch.as_tensor(s.I).to(device)
             xs.append(net.preprocess(I))
             ts.append(torch.as_tensor(t).to(device))
-        if targets == "dm":
+        if targets.startswith("dm"):
             batch.free()
         log(f"pairs: scans {g0}..{g0 + len(scans) - 1}: generate {t1 - t0:.1f} s, "
             f"targets {time.time() - t1:.1f} s")
@@ -327,7 +346,7 @@ def main(argv=None):
     ap.add_argument("--train-frames", type=int, default=256)
     ap.add_argument("--train-obj", type=int, default=384)
     ap.add_argument("--dm-iters", type=int, default=100)
-    ap.add_argument("--targets", choices=["truth", "dm"], default="truth")
+    ap.add_argument("--targets", choices=["dm-masked", "dm", "truth"], default="dm-masked")
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -367,7 +386,7 @@ def main(argv=None):
         report["training"] = {
             "scans": a.train_scans, "frames_per_scan": a.train_frames,
             "object": a.train_obj, "targets": a.targets,
-            "dm_iters": a.dm_iters if a.targets == "dm" else None, "pairs": int(x.shape[0]),
+            "dm_iters": a.dm_iters if a.targets.startswith("dm") else None, "pairs": int(x.shape[0]),
             "validation_pairs": int(xv.shape[0]), "epochs": a.epochs, "batch": a.batch,
             "lr": a.lr, "steps": steps, "pairs_s": t_pairs, "train_s": t_train,
             "samples_per_s": steps * a.batch / t_train, "val_loss_initial": v0,

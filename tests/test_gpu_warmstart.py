@@ -49,26 +49,27 @@ def test_warm_start_pipeline_small():
 
 
 def test_warm_start_gain():
-    """Trained on the synthetic scans' own objects (masked to the probe's
-    footprint), the network beats the flat object on held-out pairs, and its
-    stitched start is closer to the true object than the flat start, before
-    and after the first iteration, with a smaller first probe change."""
+    """Trained on the objects DM itself reconstructs from synthetic scans
+    (phase ramp removed, masked to the probe's footprint), the network beats
+    the flat object on held-out pairs, and its stitched start is closer to the
+    true object than the flat start, before and after the first iteration,
+    with a smaller first probe change."""
     import torch
     from paper_1808_10375_amd.dmnet import DMNet
     dev = "cuda:0"
-    net = DMNet(32, size=64, base_ch=16, levels=4, lr=1e-3, device=dev)
-    net.set_params(ws.initial_params(11, 16, 4))
+    net = DMNet(32, size=64, base_ch=32, levels=4, lr=1e-3, device=dev)
+    net.set_params(ws.initial_params(11, 32, 4))
     x, t = ws.make_pairs(list(range(10100, 10164)), n_frames=256, obj=384, net=net,
                          device=dev)
     xv, tv = ws.make_pairs([20100, 20101], n_frames=256, obj=384, net=net, device=dev)
     flat = torch.zeros_like(tv)
     flat[:, 0] = 1.0
     flat_loss = float(torch.mean((flat - tv) ** 2))
-    hist, steps, secs = ws.train(net, x, t, xv, tv, epochs=10, batch=32, log_every=1000)
+    hist, steps, secs = ws.train(net, x, t, xv, tv, epochs=14, batch=32, log_every=1000)
     v1 = hist[-1]["val_loss"]
     say(f"  validation loss {v1:.5f} against {flat_loss:.5f} for the flat object "
         f"({steps} steps, {secs:.1f} s)")
-    assert np.isfinite(v1) and v1 < 0.9 * flat_loss
+    assert np.isfinite(v1) and v1 < 0.95 * flat_loss
     scans = [ws.training_scan(30100 + k, 400, 512) for k in range(2)]
     rep = ws.compare(net, scans, n_iter=10, batch=32, device=dev, checkpoints=(1, 5))
     for r in rep["per_scan"]:
@@ -76,8 +77,8 @@ def test_warm_start_gain():
         ec, ew = r["err_at"]["cold"], r["err_at"]["warm"]
         say(f"  {r['frames']} views: object error cold {oc} warm {ow}; err cold {ec} "
             f"warm {ew}")
-        assert ow["0"] < 0.9 * oc["0"]
-        assert ow["1"] < 0.9 * oc["1"]
+        assert ow["0"] < 0.95 * oc["0"]
+        assert ow["1"] < 0.95 * oc["1"]
         assert ew["1"] < ec["1"]
 
 

@@ -264,10 +264,10 @@ def bench_warm_start(scans, ms_per_iter: float, n_iter: int = 100, train_scans: 
                      epochs: int = 8):
     """The learned warm start on the 16 uneven scans: the network is trained
     here (pairs from `train_scans` synthetic scans of the same family, each
-    binned frame against the true object under its window, masked to the
-    probe's footprint), then every scan runs n_iter iterations from the flat
-    object (cold) and from the stitched predictions (warm), same initial
-    probe.  err <= 1e-3 is out of reach of Poisson data, so the level is 1.1 x
+    binned frame against the object that DM reconstructs under its window,
+    phase ramp removed and masked to the probe's footprint), then every scan
+    runs n_iter iterations from the flat object (cold) and from the stitched
+    predictions (warm), same initial probe.  err <= 1e-3 is out of reach of Poisson data, so the level is 1.1 x
     the cold run's err after n_iter iterations (no FP64 reference exists for
     these 28,031 views); time to it = the warm start's inference and stitch
     time + iterations x the batched form's time per iteration."""
@@ -294,7 +294,7 @@ def bench_warm_start(scans, ms_per_iter: float, n_iter: int = 100, train_scans: 
     return {
         "workload": "the 16 uneven scans of the batched form",
         "network": {"levels": 4, "channels": [32, 64, 128, 256], "params": net.n_params},
-        "training": {"pairs": n_pairs, "scans": train_scans, "epochs": epochs, "steps": steps,
+        "training": {"pairs": n_pairs, "scans": train_scans, "targets": "dm-masked", "epochs": epochs, "steps": steps,
                      "pairs_s": t_pairs, "train_s": t_train,
                      "val_loss": hist[-1]["val_loss"], "val_loss_flat_object": flat_loss},
         "inference_and_stitch_s": rep["warm_init_s"],

@@ -668,7 +668,7 @@ template <int F>
 dm_status launch_views_mixed(dm_ctx* c) {
   using C = dmk::Mix<F>;
   const int M = c->M;
-  hipLaunchKernelGGL(dmk::k_mix_rows_fwd<F>, dim3(c->total_views * M, C::NBLK), dim3(C::NT), 0,
+  hipLaunchKernelGGL(dmk::k_mix_rows_fwd<F>, dim3(c->total_views, C::NBLK), dim3(C::NT), 0,
                      c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_mix_rows_fwd");
   const int cb = mix_cols_per_block(F, M);

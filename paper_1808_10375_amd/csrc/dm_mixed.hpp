@@ -215,8 +215,9 @@ __device__ __forceinline__ void mix_inverse(float2 (&a)[Mix<F>::R], float2* line
   if (active && t < Q) mix_last_inv<F>(a, line, twl, t);
 }
 
-// (1) Z = 2 P O - psi and the DFT along rows; RB rows of one view-mode per
-// block, Q + 1 threads per row.
+// (1) Z = 2 P O - psi and the DFT along rows; RB rows of every mode of one
+// view per block, Q + 1 threads per row, mode after mode with the next
+// mode's psi in flight (the tables are loaded once per block).
 template <int F>
 __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
     const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
@@ -227,45 +228,57 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
   __shared__ float2 twl[F];
   __shared__ float2 twq[Q];
   const int t = threadIdx.x;
-  const int2 vm = vmap[blockIdx.x / M];
+  const int2 vm = vmap[blockIdx.x];
   const ScanDev& sc = scans[vm.x];
-  const int j = uni(vm.y), m = blockIdx.x % M;
-  const int jm = j * M + m;
+  const int j = uni(vm.y);
   const int rl = t / QT, tl = t % QT;
   const int row = blockIdx.y * RB + rl;
   const bool active = rl < RB && row < F;
+  const bool owner = active && tl < Q;
   float2* line = xb + rl * LS;
   mix_load_tables<F>(tw, twl, twq, t, C::NT);
-  float2 a[R] = {};
-  if (active && tl < Q) {
-    const int W = uni(sc.W);
-    const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
-    const float2* __restrict__ pm = sc.psi + (size_t)jm * FF + (size_t)row * F;
-    const float2* __restrict__ Pm = sc.P + (size_t)m * FF + (size_t)row * F;
-    const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
+  const int W = uni(sc.W);
+  const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
+  const float2* __restrict__ p0 = sc.psi + (size_t)j * M * FF + (size_t)row * F;
+  const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
+  float2 psn[R];
+  if (owner) {
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) {
-      const int v = Q * n1 + tl;
-      const float2 phi = cmul(Pm[v], Or[v]);
-      const float2 ps = pm[v];
-      a[n1] = make_float2(2.f * phi.x - ps.x, 2.f * phi.y - ps.y);
-    }
+    for (int n1 = 0; n1 < R; ++n1) psn[n1] = p0[Q * n1 + tl];
   }
-  __syncthreads();  // tables
-  if (active && tl < Q) mix_first<F, -1>(a, line, twl, tl);
-  __syncthreads();
-  if (active) mix_uv<F>(line, tl);
-  __syncthreads();
-  if (active) {
-    float2 lo[H], hi[H];
-    mix_pairs<F, -1>(lo, hi, line, twq, tl);
-    int ilo, ihi;
-    mix_pair_pos<F>(tl, ilo, ihi);
-    float2* __restrict__ Tr = sc.tspec + (size_t)jm * FF + (size_t)row * F;
+  for (int m = 0; m < M; ++m) {
+    const int jm = j * M + m;
+    float2 a[R] = {};
+    if (owner) {
+      const float2* __restrict__ Pm = sc.P + (size_t)m * FF + (size_t)row * F;
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      Tr[ilo + k] = lo[k];
-      if (ihi >= 0) Tr[ihi + k] = hi[k];
+      for (int n1 = 0; n1 < R; ++n1) {
+        const int v = Q * n1 + tl;
+        const float2 phi = cmul(Pm[v], Or[v]);
+        a[n1] = make_float2(2.f * phi.x - psn[n1].x, 2.f * phi.y - psn[n1].y);
+      }
+      if (m + 1 < M) {
+        const float2* __restrict__ pq = p0 + (size_t)(m + 1) * FF;
+#pragma unroll
+        for (int n1 = 0; n1 < R; ++n1) psn[n1] = pq[Q * n1 + tl];
+      }
+    }
+    __syncthreads();  // tables; the previous mode's reads of the lines are done
+    if (owner) mix_first<F, -1>(a, line, twl, tl);
+    __syncthreads();
+    if (active) mix_uv<F>(line, tl);
+    __syncthreads();
+    if (active) {
+      float2 lo[H], hi[H];
+      mix_pairs<F, -1>(lo, hi, line, twq, tl);
+      int ilo, ihi;
+      mix_pair_pos<F>(tl, ilo, ihi);
+      float2* __restrict__ Tr = sc.tspec + (size_t)jm * FF + (size_t)row * F;
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        Tr[ilo + k] = lo[k];
+        if (ihi >= 0) Tr[ihi + k] = hi[k];
+      }
     }
   }
 }

@@ -426,13 +426,11 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
 #pragma unroll
       for (int h = 0; h < R / 2; ++h) d[h] = Tr[h];
     }
-    __syncthreads();  // the rows (and, in the first mode, the tables)
-    float2 a[R] = {};
-    mix_inverse<F>(a, line, twl, twq, tl, active);  // a[n1] = Z' at column Q n1 + tl
+    // the update's operands go out before the transform
+    float2* __restrict__ pm = sc.psi + base;
+    float2 pr[R], ov[R], pv[R];
     if (owner) {
-      float2* __restrict__ pm = sc.psi + base;
       const float2* __restrict__ Pm = sc.P + (size_t)m * FF + (size_t)row * F;
-      float2 pr[R], ov[R], pv[R];
 #pragma unroll
       for (int n1 = 0; n1 < R; ++n1) {
         const int v = Q * n1 + tl;
@@ -440,6 +438,11 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
         ov[n1] = Or[v];
         pv[n1] = pm[v];
       }
+    }
+    __syncthreads();  // the rows (and, in the first mode, the tables)
+    float2 a[R] = {};
+    mix_inverse<F>(a, line, twl, twq, tl, active);  // a[n1] = Z' at column Q n1 + tl
+    if (owner) {
 #pragma unroll
       for (int n1 = 0; n1 < R; ++n1) {
         const float2 phi = cmul(pr[n1], ov[n1]);

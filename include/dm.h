@@ -108,7 +108,10 @@ typedef enum {
                                     of each dm_iterate call (by default:
                                     every iteration).  The other iterations
                                     then run the merged streamed view kernels
-                                    (F <= 128) without a second read of psi:
+                                    (F <= 128) and the three-kernel paths
+                                    (rows / columns / rows, all F) without a
+                                    second read of psi (the fused view kernel
+                                    and the BF16x3 form still read it):
                                     psi' = (2 - beta) P O + F^-1[(beta g -
                                     1/F^2) F(2 P O - psi)], g the F_c scale,
                                     which is Eq. 3 rewritten; psi' - psi is

@@ -643,8 +643,10 @@ dm_status launch_views_fused(dm_ctx* c) {
   return DM_OK;
 }
 
+// direct: psi' without a second read of psi (the eps_psi partials are not
+// formed), as in the merged streamed kernels
 template <int F>
-dm_status launch_views_multipass(dm_ctx* c) {
+dm_status launch_views_multipass(dm_ctx* c, bool direct) {
   constexpr int B = F / 16, RB = dmk::RowCfg<F>::RB, NT = dmk::RowCfg<F>::NT;
   const int M = c->M, MT = c->M * c->L;  // probe modes, frames per view
   hipLaunchKernelGGL(dmk::k_rows_fwd<F>, dim3(c->total_views, F / RB), dim3(NT), 0,
@@ -654,10 +656,14 @@ dm_status launch_views_multipass(dm_ctx* c) {
   const int cb = cols_per_block(F, MT);
   const size_t lds = cols_lds_bytes(F, MT, cb);
   hipLaunchKernelGGL(dmk::k_cols<F>, dim3(c->total_views * (F / cb)), dim3(cb * B * MT), lds,
-                     c->stream, c->scan_dev(), c->vmap(), c->tw(), MT, cb);
+                     c->stream, c->scan_dev(), c->vmap(), c->tw(), MT, cb, direct ? 1 : 0);
   DM_LAUNCHED(c, "k_cols");
-  hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,
-                     c->scan_dev(), c->vmap(), c->tw(), M);
+  if (direct)
+    hipLaunchKernelGGL(dmk::k_rows_inv_direct<F>, dim3(c->total_views, F / RB), dim3(NT), 0,
+                       c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  else
+    hipLaunchKernelGGL(dmk::k_rows_inv<F>, dim3(c->total_views, F / RB), dim3(NT), 0, c->stream,
+                       c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_rows_inv");
   return DM_OK;
 }
@@ -665,7 +671,7 @@ dm_status launch_views_multipass(dm_ctx* c) {
 // Frames of edge F = R * Q (188, 200): the same three passes with the
 // mixed-radix line transforms.
 template <int F>
-dm_status launch_views_mixed(dm_ctx* c) {
+dm_status launch_views_mixed(dm_ctx* c, bool direct) {
   using C = dmk::Mix<F>;
   const int M = c->M;
   hipLaunchKernelGGL(dmk::k_mix_rows_fwd<F>, dim3(c->total_views, C::NBLK), dim3(C::NT), 0,
@@ -674,10 +680,14 @@ dm_status launch_views_mixed(dm_ctx* c) {
   const int cb = mix_cols_per_block(F, M);
   hipLaunchKernelGGL(dmk::k_mix_cols<F>, dim3(c->total_views * ((F + cb - 1) / cb)),
                      dim3(mix_cols_threads(F, M, cb)), mix_cols_lds_bytes(F, M, cb), c->stream,
-                     c->scan_dev(), c->vmap(), c->tw(), M, cb);
+                     c->scan_dev(), c->vmap(), c->tw(), M, cb, direct ? 1 : 0);
   DM_LAUNCHED(c, "k_mix_cols");
-  hipLaunchKernelGGL(dmk::k_mix_rows_inv<F>, dim3(c->total_views, C::NBLK), dim3(C::NT), 0,
-                     c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  if (direct)
+    hipLaunchKernelGGL(dmk::k_mix_rows_inv_direct<F>, dim3(c->total_views, C::NBLK),
+                       dim3(C::NT), 0, c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
+  else
+    hipLaunchKernelGGL(dmk::k_mix_rows_inv<F>, dim3(c->total_views, C::NBLK), dim3(C::NT), 0,
+                       c->stream, c->scan_dev(), c->vmap(), c->tw(), M);
   DM_LAUNCHED(c, "k_mix_rows_inv");
   return DM_OK;
 }
@@ -821,14 +831,16 @@ dm_status launch_views(dm_ctx* c, bool psi_err, bool* psi_valid) {
       case 128: return launch_views_fused<128>(c);
     }
   } else {
+    *psi_valid = psi_err;
+    const bool direct = !psi_err;
     switch (c->F) {
-      case 16: return launch_views_multipass<16>(c);
-      case 32: return launch_views_multipass<32>(c);
-      case 64: return launch_views_multipass<64>(c);
-      case 128: return launch_views_multipass<128>(c);
-      case 256: return launch_views_multipass<256>(c);
-      case 188: return launch_views_mixed<188>(c);
-      case 200: return launch_views_mixed<200>(c);
+      case 16: return launch_views_multipass<16>(c, direct);
+      case 32: return launch_views_multipass<32>(c, direct);
+      case 64: return launch_views_multipass<64>(c, direct);
+      case 128: return launch_views_multipass<128>(c, direct);
+      case 256: return launch_views_multipass<256>(c, direct);
+      case 188: return launch_views_mixed<188>(c, direct);
+      case 200: return launch_views_mixed<200>(c, direct);
     }
   }
   c->err = "unsupported frame size for this transform path";
@@ -836,7 +848,8 @@ dm_status launch_views(dm_ctx* c, bool psi_err, bool* psi_valid) {
 }
 
 // psi_err: form the eps_psi partial sums in this iteration (without them the
-// merged view kernels at F <= 128 skip the second read of psi)
+// merged streamed kernels and the three-kernel paths skip the second read of
+// psi)
 dm_status launch_iteration(dm_ctx* c, bool psi_err) {
   const int F = c->F, M = c->M, FF = F * F, nb = n_pblk(F);
   const int n = (int)c->scans.size();

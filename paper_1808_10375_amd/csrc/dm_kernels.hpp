@@ -956,7 +956,8 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
 template <int F>
 __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans,
                                                const int2* __restrict__ vmap,
-                                               const float2* __restrict__ tw, int M, int CB) {
+                                               const float2* __restrict__ tw, int M, int CB,
+                                               int direct) {
   constexpr int B = F / 16, FF = F * F, NI = 16 / B;
   constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_COL;
   extern __shared__ float2 dyn[];
@@ -1019,6 +1020,12 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
     for (int k2 = 0; k2 < B; ++k2) s[line * LS + (n2 + B * i) + 16 * k2] = cabs2(a[i * B + k2]);
   __syncthreads();
   const float inv_ff = 1.0f / (float)FF;
+  // g = sqrt(I / S) / F^2, or beta g - 1/F^2 for the update without psi
+  const float beta = sc.beta;
+  auto scale = [&](float iv, float sum) {
+    const float g = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    return direct ? beta * g - inv_ff : g;
+  };
 #pragma unroll
   for (int i = 0; i < KI; ++i) {
     const int p = t + i * (int)blockDim.x;
@@ -1026,16 +1033,14 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
       const int cc = p / F, kk = p - cc * F;
       float sum = 0.f;
       for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + cc) * LS + kk];
-      const float iv = fmaxf(ivp[i], 0.f);
-      gsh[cc * LS + kk] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+      gsh[cc * LS + kk] = scale(fmaxf(ivp[i], 0.f), sum);
     }
   }
   for (int p = t + KI * (int)blockDim.x; p < CB * F; p += blockDim.x) {
     const int cc = p / F, kk = p - cc * F;
     float sum = 0.f;
     for (int mm = 0; mm < M; ++mm) sum += s[(mm * CB + cc) * LS + kk];
-    const float iv = fmaxf(Ij[(size_t)kk * F + cc], 0.f);
-    gsh[cc * LS + kk] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    gsh[cc * LS + kk] = scale(fmaxf(Ij[(size_t)kk * F + cc], 0.f), sum);
   }
   __syncthreads();
   float gs[16];
@@ -1068,11 +1073,13 @@ __global__ __launch_bounds__(1024) void k_cols(const ScanDev* __restrict__ scans
 // of the view and eps_psi partial sums; all modes of RB rows per block.  With
 // L object modes the frames run l-major (c = l M + k) and the numerator of
 // object mode l, sum_k conj(P_k) psi'_{(k,l)}, is written after its M
-// frames.
-template <int F>
-__global__ __launch_bounds__(256) void k_rows_inv(
-    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
-    const float2* __restrict__ tw, int M) {
+// frames.  DIRECT: the column kernel scaled the spectra by beta g - 1/F^2,
+// so the inverse is beta Z' - Z and psi' = (2 - beta) P O + that (Eq. 3 with
+// psi = 2 P O - Z): psi is not read and the eps_psi partials are zero.
+template <int F, bool DIRECT>
+__device__ __forceinline__ void rows_inv(const ScanDev* __restrict__ scans,
+                                         const int2* __restrict__ vmap,
+                                         const float2* __restrict__ tw, int M) {
   constexpr int B = F / 16, RB = RowCfg<F>::RB, FF = F * F, NI = 16 / B;
   constexpr int XS = XCfg<F>::XS, LD = XCfg<F>::XL_ROW;
   constexpr int NT = RowCfg<F>::NT;
@@ -1125,8 +1132,10 @@ __global__ __launch_bounds__(256) void k_rows_inv(
     // the second half before the first half's stores (66.2 -> 65.5 ms for
     // the view update at 10000 x 8 x 256^2)
     float2 psn[8];
+    if constexpr (!DIRECT) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) psn[k] = ntl2(&pm[B * k + n2]);
+      for (int k = 0; k < 8; ++k) psn[k] = ntl2(&pm[B * k + n2]);
+    }
     float2 a[16];
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -1158,21 +1167,28 @@ __global__ __launch_bounds__(256) void k_rows_inv(
         const int v = B * (b + k) + n2;
         pr[k] = Pm[v];
         ov[k] = Or[v];
-        pv[k] = psn[k];
+        if constexpr (!DIRECT) pv[k] = psn[k];
       }
-      if (b == 0) {
+      if constexpr (!DIRECT) {
+        if (b == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) psn[k] = ntl2(&pm[B * (8 + k) + n2]);
+          for (int k = 0; k < 8; ++k) psn[k] = ntl2(&pm[B * (8 + k) + n2]);
+        }
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int n1 = b + k;
         const int v = B * n1 + n2;
         const float2 phi = cmul(pr[k], ov[k]);
-        const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
-        const float2 pn = cadd(pv[k], d);
+        float2 pn;
+        if constexpr (DIRECT) {
+          pn = make_float2((2.f - beta) * phi.x + a[n1].x, (2.f - beta) * phi.y + a[n1].y);
+        } else {
+          const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
+          pn = cadd(pv[k], d);
+          e_d += cabs2(d);
+        }
         nts2(pn, &pm[v]);
-        e_d += cabs2(d);
         e_n += cabs2(pn);
         oacc[n1] = cadd(oacc[n1], cmulc(pr[k], pn));
       }
@@ -1192,6 +1208,20 @@ __global__ __launch_bounds__(256) void k_rows_inv(
     err_psi[2 * part] = e_d;
     err_psi[2 * part + 1] = e_n;
   }
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_rows_inv(const ScanDev* __restrict__ scans,
+                                                  const int2* __restrict__ vmap,
+                                                  const float2* __restrict__ tw, int M) {
+  rows_inv<F, false>(scans, vmap, tw, M);
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_rows_inv_direct(const ScanDev* __restrict__ scans,
+                                                         const int2* __restrict__ vmap,
+                                                         const float2* __restrict__ tw, int M) {
+  rows_inv<F, true>(scans, vmap, tw, M);
 }
 
 // ---------------------------------------------------------------------------

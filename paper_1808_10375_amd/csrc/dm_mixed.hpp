@@ -306,7 +306,8 @@ __device__ __forceinline__ int xcd_view_slot(int b, int n, int nblk) {
 template <int F>
 __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ scans,
                                                    const int2* __restrict__ vmap,
-                                                   const float2* __restrict__ tw, int M, int CB) {
+                                                   const float2* __restrict__ tw, int M, int CB,
+                                                   int direct) {
   using C = Mix<F>;
   constexpr int R = C::R, Q = C::Q, QT = C::QT, H = C::H, LS = C::LS, FF = F * F;
   extern __shared__ __align__(16) float2 dyn[];
@@ -354,16 +355,19 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
   }
   __syncthreads();
   // one thread per pixel of the block's columns: sum over modes, scale
-  // sqrt(I / S) / F^2 (0 where S vanishes); pixels in column-major order
+  // sqrt(I / S) / F^2 (0 where S vanishes), or beta times that less 1/F^2
+  // for the update without psi; pixels in column-major order
   const float* __restrict__ Ij = sc.I + (size_t)j * FF + col0;
   const float inv_ff = 1.0f / (float)FF;
+  const float beta = sc.beta;
   for (int p = t; p < CB * F; p += blockDim.x) {
     const int cc = p / F, kk = p - cc * F;
     if (col0 + cc >= F) continue;
     float sum = 0.f;
     for (int mm = 0; mm < M; ++mm) sum += s[(size_t)(mm * CB + cc) * F + kk];
     const float iv = fmaxf(Ij[(size_t)kk * F + cc], 0.f);
-    g[cc * F + kk] = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    const float gg = (sum > FLT_MIN) ? sqrtf(iv / sum) * inv_ff : 0.f;
+    g[cc * F + kk] = direct ? beta * gg - inv_ff : gg;
   }
   __syncthreads();
   if (active) {
@@ -389,11 +393,13 @@ __global__ __launch_bounds__(1024) void k_mix_cols(const ScanDev* __restrict__ s
 // modes of RB rows per block.  The line buffers alternate between modes, so
 // a mode's spectrum rows go from global memory straight into the buffer the
 // previous mode did not use (its last readers passed the barriers of that
-// mode).
-template <int F>
-__global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
-    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
-    const float2* __restrict__ tw, int M) {
+// mode).  DIRECT: the column kernel scaled the spectra by beta g - 1/F^2, the
+// inverse is beta Z' - Z, and psi' = (2 - beta) P O + that (Eq. 3 with
+// psi = 2 P O - Z): psi is not read and the eps_psi partials are zero.
+template <int F, bool DIRECT>
+__device__ __forceinline__ void mix_rows_inv(const ScanDev* __restrict__ scans,
+                                             const int2* __restrict__ vmap,
+                                             const float2* __restrict__ tw, int M) {
   using C = Mix<F>;
   constexpr int R = C::R, Q = C::Q, QT = C::QT, RB = C::RB, LS = C::LS, NT = C::NT, FF = F * F;
   __shared__ __align__(16) float2 xb[2 * RB * LS];
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
         const int v = Q * n1 + tl;
         pr[n1] = Pm[v];
         ov[n1] = Or[v];
-        pv[n1] = pm[v];
+        if constexpr (!DIRECT) pv[n1] = pm[v];
       }
     }
     __syncthreads();  // the rows (and, in the first mode, the tables)
@@ -446,10 +452,15 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
 #pragma unroll
       for (int n1 = 0; n1 < R; ++n1) {
         const float2 phi = cmul(pr[n1], ov[n1]);
-        const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
-        const float2 pn = cadd(pv[n1], d);
+        float2 pn;
+        if constexpr (DIRECT) {
+          pn = make_float2((2.f - beta) * phi.x + a[n1].x, (2.f - beta) * phi.y + a[n1].y);
+        } else {
+          const float2 d = make_float2(beta * (a[n1].x - phi.x), beta * (a[n1].y - phi.y));
+          pn = cadd(pv[n1], d);
+          e_d += cabs2(d);
+        }
         pm[Q * n1 + tl] = pn;
-        e_d += cabs2(d);
         e_n += cabs2(pn);
         oacc[n1] = cadd(oacc[n1], cmulc(pr[n1], pn));
       }
@@ -466,6 +477,21 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(
     sc.err_psi[2 * part] = e_d;
     sc.err_psi[2 * part + 1] = e_n;
   }
+}
+
+template <int F>
+__global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv(const ScanDev* __restrict__ scans,
+                                                             const int2* __restrict__ vmap,
+                                                             const float2* __restrict__ tw,
+                                                             int M) {
+  mix_rows_inv<F, false>(scans, vmap, tw, M);
+}
+
+template <int F>
+__global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_inv_direct(
+    const ScanDev* __restrict__ scans, const int2* __restrict__ vmap,
+    const float2* __restrict__ tw, int M) {
+  mix_rows_inv<F, true>(scans, vmap, tw, M);
 }
 
 }  // namespace dmk

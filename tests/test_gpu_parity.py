@@ -406,6 +406,21 @@ def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
     same call without the flag (the direct form in every iteration): states
     to the one-step bar, eps_psi NaN in the first two iterations with the
     flag only, and equal to the oracle's wherever it is formed."""
+    psi_free_case(seed, n, f, m, h, w, view_path)
+
+
+@pytest.mark.parametrize("seed,n,f,m,h,w", [(44, 11, 64, 3, 170, 160), (45, 5, 256, 2, 400, 380),
+                                            (46, 6, 188, 2, 300, 290), (47, 6, 200, 3, 320, 300)])
+def test_psi_free_update_three_kernel_paths(seed, n, f, m, h, w):
+    """The same rewritten update on the three-kernel paths (power-of-two
+    rows / columns / rows at F = 64 and 256, mixed radix at 188 and 200):
+    the column kernel scales the spectra by beta g - 1/F^2 and the inverse
+    row kernel forms psi' from P O and the transform alone."""
+    from paper_1808_10375_amd import dm
+    psi_free_case(seed, n, f, m, h, w, 1, dm.DM_FLAG_MULTIPASS if f <= 128 else 0)
+
+
+def psi_free_case(seed, n, f, m, h, w, view_path, init_flags=0):
     from paper_1808_10375_amd import dm
     torch = _torch()
     say(f"case psi-free update view_path={view_path} seed={seed} N={n} F={f} M={m}")
@@ -423,7 +438,7 @@ def test_psi_free_update_over_three_iterations(seed, n, f, m, h, w, view_path):
         It = torch.from_numpy(np.ascontiguousarray(c["I"], dtype=np.float32)).to(dev)
         Pt = torch.from_numpy(np.ascontiguousarray(c["P"], dtype=np.complex64)).to(dev)
         Ot = torch.from_numpy(np.ascontiguousarray(c["O"], dtype=np.complex64)).to(dev)
-        ctx = dm.DMContext(It, c["pos"], Pt, Ot, beta=c["beta"], flags=flags)
+        ctx = dm.DMContext(It, c["pos"], Pt, Ot, beta=c["beta"], flags=flags | init_flags)
         t = ctx.tuning()
         ctx.set_tuning(t["obj_tile"], t["probe_chunks"], view_path)
         ctx.set_state(torch.from_numpy(np.ascontiguousarray(c["psi"])).to(dev), Pt, Ot, 0)

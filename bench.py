@@ -478,7 +478,21 @@ def bench_flyscan_256(steps: int, warmup: int):
                 f"n{n}_m{m}_f{f}_o{scan.obj_shape[0]}x{scan.obj_shape[1]}",
                 "views (3 kernels)")),
             "step_roofline_frac": step_alg_bytes(n, m, f) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "phase_ms_per_iter": {k: v / max(r["n_timed"], 1) for k, v in r["phases"].items()}}
+            "phase_ms_per_iter": {k: v / max(r["n_timed"], 1) for k, v in r["phases"].items()},
+            "psi_error_last": psi_error_last_form(scan, steps, warmup)}
+
+
+def psi_error_last_form(scan, steps: int, warmup: int):
+    """A scan again with DM_FLAG_PSI_ERROR_LAST: eps_psi only in the last of
+    the `steps` timed iterations (one call), the others update psi without
+    reading it a second time."""
+    from paper_1808_10375_amd import dm
+    n, m = scan.n_frames, scan.n_modes
+    r = run_scan(scan, steps, warmup, 0, dm.DM_FLAG_PSI_ERROR_LAST)
+    ms = 1e3 * r["elapsed"] / steps
+    return {"value": n * m / (ms * 1e-3), "unit": "frame·mode/s", "ms_per_step": ms,
+            "views_ms": r["phases"]["views"] / max(r["n_timed"], 1),
+            "eps_psi": f"formed in 1 of the {steps} timed iterations"}
 
 
 def main():

@@ -10,7 +10,8 @@ import pytest
 
 from oracle import dm_oracle as oracle
 from paper_1808_10375_amd import synth
-from test_gpu_parity import PROBE_FIRST, gpu_one_step, one_step_case, rel, rel_weighted
+from test_gpu_parity import (PROBE_FIRST, gpu_one_step, one_step_case, psi_free_case, rel,
+                             rel_weighted)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +43,18 @@ CASES = [
 def test_one_step_object_modes(seed, n, f, m, L, h, w):
     say(f"case object modes seed={seed} N={n} F={f} M={m} L={L} obj={h}x{w}")
     one_step_case(synth.random_case(seed, n, f, m, h, w, n_obj_modes=L))
+
+
+@pytest.mark.parametrize("seed,n,f,m,L,h,w", [(12, 13, 64, 2, 2, 150, 140),
+                                              (13, 5, 256, 2, 2, 300, 290)])
+def test_psi_free_update_object_modes(seed, n, f, m, L, h, w):
+    """DM_FLAG_PSI_ERROR_LAST with L object modes: every frame (k, l) of a
+    view takes the scale beta g - 1/F^2 and psi' = (2 - beta) P_k O_l + the
+    inverse, over three iterations against the oracle and the same call
+    without the flag."""
+    from paper_1808_10375_amd import dm
+    psi_free_case(seed, n, f, m, h, w, 1, dm.DM_FLAG_MULTIPASS if f <= 128 else 0,
+                  n_obj_modes=L)
 
 
 @pytest.mark.parametrize("seed,n,f,m,L,h,w", [(7, 11, 64, 2, 2, 130, 120),

@@ -420,11 +420,12 @@ def test_psi_free_update_three_kernel_paths(seed, n, f, m, h, w):
     psi_free_case(seed, n, f, m, h, w, 1, dm.DM_FLAG_MULTIPASS if f <= 128 else 0)
 
 
-def psi_free_case(seed, n, f, m, h, w, view_path, init_flags=0):
+def psi_free_case(seed, n, f, m, h, w, view_path, init_flags=0, n_obj_modes=1):
     from paper_1808_10375_amd import dm
     torch = _torch()
-    say(f"case psi-free update view_path={view_path} seed={seed} N={n} F={f} M={m}")
-    c = synth.random_case(seed, n, f, m, h, w, perturb=0.3)
+    say(f"case psi-free update view_path={view_path} seed={seed} N={n} F={f} M={m} "
+        f"L={n_obj_modes}")
+    c = synth.random_case(seed, n, f, m, h, w, perturb=0.3, n_obj_modes=n_obj_modes)
     psi, P, O = (c["psi"].astype(np.complex128), c["P"].astype(np.complex128),
                  c["O"].astype(np.complex128))
     hist_o = []

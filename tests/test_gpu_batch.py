@@ -165,17 +165,19 @@ def test_probe_first_batch_graphs_equal_eager_and_oracle():
     e.free()
 
 
-def test_graphs_with_psi_error_last_equal_eager_launches():
+@pytest.mark.parametrize("f,objs", [(128, (200, 180)), (188, (300, 280))])
+def test_graphs_with_psi_error_last_equal_eager_launches(f, objs):
     """DM_FLAG_PSI_ERROR_LAST with graph replay: each context keeps one graph
     without and one with the eps_psi partials (the last iteration of a
     call).  Calls of 3 and 2 iterations replayed against the same calls
     launched eagerly: bitwise equal states and errors, eps_psi NaN in every
-    iteration but the last of each call; and within 1e-5 of the direct
-    update in every iteration (no flag)."""
+    iteration but the last of each call; and within 1e-5 of the update that
+    reads psi in every iteration (no flag).  F = 128 runs the merged
+    streamed kernel, F = 188 the mixed-radix three-kernel path."""
     torch = _torch()
     from paper_1808_10375_amd import dm
-    scans = uneven_scans(seed=70, sizes=(9, 14), f=128, m=2, objs=(200, 180))
-    say("case graphs with DM_FLAG_PSI_ERROR_LAST vs eager, calls of 3 and 2 iterations")
+    scans = uneven_scans(seed=70, sizes=(9, 14), f=f, m=2, objs=objs)
+    say(f"case graphs with DM_FLAG_PSI_ERROR_LAST vs eager, F={f}, calls of 3 and 2 iterations")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         g = dm.DMBatch(scans, flags=dm.DM_FLAG_GRAPH | dm.DM_FLAG_PSI_ERROR_LAST,

@@ -291,6 +291,29 @@ def test_beta_zero_leaves_views_unchanged():
     assert rel(dm.view_update(psi, P, O, pos, I, 0.0), psi) == 0.0
 
 
+@pytest.mark.parametrize("beta", [0.5, 0.8, 1.0])
+def test_view_update_without_psi_after_the_transform(beta):
+    """Eq. 3 rewritten as the view kernels evaluate it when eps_psi is not
+    formed: since Z = 2 phi - psi and the transforms are linear,
+    psi' = (2 - beta) phi + F^-1[(beta s - 1) F Z], s the F_c factor
+    sqrt(I / sum_k |F Z_k|^2).  Evaluated here with explicit DFT matrices
+    (zero intensity at some pixels, where s = 0 and the factor is -1) and
+    compared with the oracle's view update."""
+    psi, P, O, pos, I = _random_state(seed=12)
+    I[:, 0, 3] = 0.0
+    I[:, 5, :] = 0.0
+    f = P.shape[-1]
+    k = np.arange(f)
+    Wf = np.exp(-2j * np.pi * np.outer(k, k) / f)
+    Wb = np.conj(Wf) / f
+    phi = np.stack([P * O[y:y + f, x:x + f][None] for (y, x) in pos])
+    zt = Wf @ (2.0 * phi - psi) @ Wf.T
+    S = np.sum(np.abs(zt) ** 2, axis=1, keepdims=True)
+    sc = np.sqrt(I[:, None] / S)
+    direct = (2.0 - beta) * phi + Wb @ ((beta * sc - 1.0) * zt) @ Wb.T
+    assert rel(direct, dm.view_update(psi, P, O, pos, I, beta)) < 1e-13
+
+
 def test_scale_invariance():
     """(cP, O/c) gives the same exit waves, hence the same psi'; the object
     and probe updates return O'/c and cP'."""

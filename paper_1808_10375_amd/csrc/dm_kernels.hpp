@@ -868,7 +868,9 @@ struct XCfg {
 // (1) Z = 2 P O - psi and the DFT along rows: RB rows of every frame of one
 // view per block, frame after frame, the next frame's psi rows loaded while
 // the current one is transformed (at 10000 x 8 x 256^2: 66.1 ms for the view
-// update against 68.8 ms with one block per frame).  M is the number of
+// update against 68.8 ms with one block per frame).  The object rows are
+// loaded once per object mode and held across its probe modes (both row
+// kernels: 62.0 -> 60.6 ms).  M is the number of
 // probe modes; with L object modes a view holds L M frames, frame c = l M + k
 // being the pair of probe mode k and object mode l.
 template <int F>
@@ -896,19 +898,24 @@ __global__ __launch_bounds__(256) void k_rows_fwd(
   constexpr int LT = F + 1;
   static_assert(LT <= LD, "the tile fits the exchange buffer");
   const int r = t % RB, kg = t / RB;
-  float2 pn[16];
+  float2 pn[16], ov[16];
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) pn[n1] = ntl2(&p0[B * n1 + n2]);
   for (int mc = 0; mc < MT; ++mc) {
     const int m = mc % M, l = mc / M;
     const int jm = j * MT + mc;
     const float2* __restrict__ Pm = P + (size_t)m * FF + (size_t)row * F;
-    const float2* __restrict__ Or = O + (size_t)l * uni(sc.H) * W + (size_t)(y0 + row) * W + x0;
+    if (m == 0) {
+      const float2* __restrict__ Or =
+          O + (size_t)l * uni(sc.H) * W + (size_t)(y0 + row) * W + x0;
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) ov[n1] = Or[B * n1 + n2];
+    }
     float2 a[16];
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) {
       const int v = B * n1 + n2;
-      const float2 phi = cmul(Pm[v], Or[v]);
+      const float2 phi = cmul(Pm[v], ov[n1]);
       a[n1] = make_float2(2.f * phi.x - pn[n1].x, 2.f * phi.y - pn[n1].y);
     }
     if (mc + 1 < MT) {
@@ -1105,13 +1112,17 @@ __device__ __forceinline__ void rows_inv(const ScanDev* __restrict__ scans,
   const int y0 = uni(pos[2 * j]), x0 = uni(pos[2 * j + 1]);
   const int L = uni(sc.L), MT = M * L;
   const size_t HW = (size_t)uni(sc.H) * W;
-  float2 oacc[16];
+  float2 oacc[16], ovh[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) oacc[r] = make_float2(0.f, 0.f);
   float e_d = 0.f, e_n = 0.f;
   for (int mc = 0; mc < MT; ++mc) {
     const int m = mc % M, l = mc / M;
-    const float2* __restrict__ Or = O + (size_t)l * HW + (size_t)(y0 + row) * W + x0;
+    if (m == 0) {
+      const float2* __restrict__ Or = O + (size_t)l * HW + (size_t)(y0 + row) * W + x0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ovh[r] = Or[B * r + n2];
+    }
     const size_t base = ((size_t)j * MT + mc) * FF + (size_t)row * F;
     // the block's RB x F tile, read along the k-major lines (thread (r, kg)
     // loads T[l][row0 + r] for l = kg + B s) and transposed through LDS
@@ -1166,7 +1177,7 @@ __device__ __forceinline__ void rows_inv(const ScanDev* __restrict__ scans,
       for (int k = 0; k < 8; ++k) {
         const int v = B * (b + k) + n2;
         pr[k] = Pm[v];
-        ov[k] = Or[v];
+        ov[k] = ovh[b + k];
         if constexpr (!DIRECT) pv[k] = psn[k];
       }
       if constexpr (!DIRECT) {

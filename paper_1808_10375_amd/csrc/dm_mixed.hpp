@@ -241,10 +241,17 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
   const int y0 = uni(kidx(sc.pos)[2 * j]), x0 = uni(kidx(sc.pos)[2 * j + 1]);
   const float2* __restrict__ p0 = sc.psi + (size_t)j * M * FF + (size_t)row * F;
   const float2* __restrict__ Or = sc.O + (size_t)(y0 + row) * W + x0;
-  float2 psn[R];
+  // at R = 4 the object row values are held across the modes (188^2 x 4
+  // modes: 27.9 -> 27.6 ms for the view update); at R = 8 holding them
+  // costs a wave per SIMD and was slower
+  constexpr bool kHoldO = R <= 4;
+  float2 psn[R], ov[R];
   if (owner) {
 #pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) psn[n1] = p0[Q * n1 + tl];
+    for (int n1 = 0; n1 < R; ++n1) {
+      psn[n1] = p0[Q * n1 + tl];
+      if constexpr (kHoldO) ov[n1] = Or[Q * n1 + tl];
+    }
   }
   for (int m = 0; m < M; ++m) {
     const int jm = j * M + m;
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(Mix<F>::NT) void k_mix_rows_fwd(
 #pragma unroll
       for (int n1 = 0; n1 < R; ++n1) {
         const int v = Q * n1 + tl;
-        const float2 phi = cmul(Pm[v], Or[v]);
+        const float2 phi = cmul(Pm[v], kHoldO ? ov[n1] : Or[v]);
         a[n1] = make_float2(2.f * phi.x - psn[n1].x, 2.f * phi.y - psn[n1].y);
       }
       if (m + 1 < M) {
